@@ -1,0 +1,162 @@
+/*
+ * pdsink.h - C ABI of the MI355X (gfx950) persistence-diagram Sinkhorn library.
+ *
+ * Method: Lacombe, Cuturi, Oudot, "Large Scale computation of Means and
+ * Clusters for Persistence Diagrams using Optimal Transport" (NeurIPS 2018).
+ * A diagram is a d x d histogram on [0,1]^2 plus a diagonal bin Delta
+ * (section 3, "Discretization"); the Gibbs kernel K of the (d^2+1)-point
+ * ground space is applied in separable form (Proposition 2) and the
+ * transport cost in separable form (Proposition 3).
+ *
+ * Conventions for every entry point below:
+ *  - Pointers marked (device) are device memory of the context's GPU;
+ *    pointers marked (host) are host memory.  The caller owns every buffer;
+ *    the library owns only the context's small constant tables.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued on it and its outputs are valid once it has completed.
+ *  - Return 0 on success, a negative PDSINK_E* code otherwise.  Argument
+ *    errors are detected on the host before anything is enqueued; nothing is
+ *    thrown across the boundary.  pdsink_strerror() names each code.
+ *  - Histograms are float32, row-major d x d, row index = birth cell,
+ *    column index = death cell: cell (i, j) holds the mass of the points
+ *    with floor(birth d) = i and floor(death d) = j (index d-1 for 1.0).
+ *  - Ground cost (readings of section 3): c(i,k) = (|i-k|/d)^p per axis, so
+ *    C((i,j),(k,l)) = c(i,k) + c(j,l), and the diagonal cost
+ *    c_Delta(i,j) = 2 (|j-i|/(2d))^p; gamma is in the same cost units.
+ *  - A context is immutable after creation; calls on different streams are
+ *    safe when each uses its own workspace.
+ */
+#ifndef PDSINK_H
+#define PDSINK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PDSINK_OK        0
+#define PDSINK_EINVAL   -1   /* bad argument (size, pointer, parameter, point) */
+#define PDSINK_ENOMEM   -2   /* workspace too small or device allocation failed */
+#define PDSINK_EDEVICE  -3   /* HIP runtime error (launch, copy, device) */
+#define PDSINK_ERANGE   -4   /* a result was not representable (see status bits) */
+
+/* Precision of the grid contractions (the two GEMMs of Proposition 2). */
+#define PDSINK_FP32        0  /* FP32 operands on MFMA, FP32 accumulation          */
+#define PDSINK_BF16_REFINE 1  /* BF16 operands until err <= switch_tol, then FP32  */
+
+/* Per-pair status bits written by sinkhorn_dist_batch / kmeans_assign. */
+#define PDSINK_ST_CONVERGED  0  /* err <= tol                                      */
+#define PDSINK_ST_MAX_ITER   1  /* stopped at max_iter with err > tol              */
+#define PDSINK_ST_NONFINITE  2  /* a kernel product vanished or overflowed: cost = NaN */
+#define PDSINK_ST_RANGE      4  /* scaling residual left the representable range  */
+
+typedef struct pdsink_ctx pdsink_ctx;
+
+typedef struct {
+  int32_t d;            /* grid size, 2 <= d <= 128                                    */
+  double  p;            /* ground exponent, p >= 1 (the paper's experiments use 2)     */
+  double  gamma;        /* entropic parameter, > 0, in cost units of [0,1]^2           */
+  double  tol;          /* stop when (||P1-a||_1 + |.|_Delta)/m <= tol; 0 = run max_iter */
+  int32_t max_iter;     /* cap on full (u, v) iterations, >= 1                         */
+  int32_t precision;    /* PDSINK_FP32 or PDSINK_BF16_REFINE                           */
+  double  switch_tol;   /* BF16_REFINE: switch to FP32 once err <= switch_tol          */
+} pdsink_params;
+
+/* Create a context for `params` on HIP device `device`: validates the
+ * parameters and uploads the per-(d, gamma, p) tables of the 1-D kernels
+ * k = exp(-c/gamma), k_Delta and costs c, c_Delta (section 3, the tables
+ * before Propositions 2 and 3), as exact (exponent, mantissa) pairs.
+ * (host) params, (host) out.  Returns PDSINK_EINVAL for d outside [2, 128],
+ * p < 1, gamma <= 0, tol < 0, max_iter < 1 or an unknown precision. */
+int pdsink_ctx_create(const pdsink_params* params, int device, pdsink_ctx** out);
+
+/* Release the context's device tables.  NULL is a no-op. */
+void pdsink_ctx_destroy(pdsink_ctx* ctx);
+
+/* Parameters the context was created with (host out). */
+int pdsink_ctx_params(const pdsink_ctx* ctx, pdsink_params* out);
+
+#define PDSINK_OP_DIST        0
+#define PDSINK_OP_KMEANS      1
+#define PDSINK_OP_BARYCENTER  2
+/* Workspace (device bytes) an operation needs for `n_items` (pairs for DIST,
+ * diagrams x centroids for KMEANS, diagrams for BARYCENTER).  (host) bytes. */
+int pdsink_workspace_bytes(const pdsink_ctx* ctx, int op, int64_t n_items, size_t* bytes);
+
+/* Discretisation (section 3, "Discretization"; supplementary, error control
+ * due to discretisation).  Diagram n owns points [offsets[n], offsets[n+1])
+ * of `pts`, each (birth, death) in float32.  Writes hist[n] (d x d counts,
+ * overwritten) and mass[n] = number of points kept.  A point outside [0,1]^2,
+ * non-finite, or with birth > death is not counted; the number of such points
+ * is added to *n_bad.  The cell index floor(x d) is taken in exact arithmetic.
+ *   pts     (device) float32 [total, 2]
+ *   offsets (device) int64   [n_diag + 1], non-decreasing, offsets[0] = 0
+ *   hist    (device) float32 [n_diag, d, d]  out
+ *   mass    (device) double  [n_diag]        out
+ *   n_bad   (device) int32   [1]             in/out (accumulated), may be NULL
+ * n_diag = 0 is a no-op. */
+int pd_discretize(pdsink_ctx* ctx, const float* pts, const int64_t* offsets, int64_t n_diag,
+                  float* hist, double* mass, int32_t* n_bad, void* stream);
+
+/* Algorithm 1 for a batch of pairs.  Pair q transports
+ * a = (hist_a[ia[q]], |hist_b[ib[q]]|) onto b = (hist_b[ib[q]], |hist_a[ia[q]]|)
+ * (Proposition 1: D1 + R D2 onto D2 + R D1).  Iterates the Sinkhorn map
+ * (section 2) in alternating form from v = 1, u-update first, applying K by
+ * Proposition 2, until the marginal error dist(P, Pi(a,b)) / m <= tol or
+ * max_iter iterations, then returns the Sinkhorn cost <P_t, C> of
+ * Proposition 3, reduced in FP64.
+ *   hist_a, hist_b (device) float32 [*, d, d]  histogram pools (may alias)
+ *   ia, ib         (device) int32   [n_pairs]  indices into the pools
+ *   cost           (device) double  [n_pairs]  out: <P_t, C>
+ *   iters          (device) int32   [n_pairs, 2] out: iterations in BF16, in FP32
+ *   err            (device) float   [n_pairs]  out: marginal error / m at stopping
+ *   status         (device) int32   [n_pairs]  out: PDSINK_ST_* bits
+ *   ws, ws_bytes   (device) workspace of at least pdsink_workspace_bytes(DIST)
+ * Masses are the histogram sums.  n_pairs = 0 is a no-op. */
+int sinkhorn_dist_batch(pdsink_ctx* ctx, int64_t n_pairs,
+                        const float* hist_a, const float* hist_b,
+                        const int32_t* ia, const int32_t* ib,
+                        double* cost, int32_t* iters, float* err, int32_t* status,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/* Algorithm 2: smoothed barycenter of the diagrams hist[0..n_diag) (section 4).
+ * Pairs (z + R a_i, a_i + R z) are iterated to `tol` of the context
+ * (warm-started), the gradient of Proposition 5 averaged over the diagrams,
+ * gamma (mean_i log u_i + log v_i,Delta), and z <- z * exp(-lambda grad).
+ * Stops when |E_t / E_{t-1} - 1| < energy_rtol or after max_outer steps,
+ * where E_t = mean_i S(z_t + R a_i, a_i + R z_t) (Algorithm 2, energy step).
+ *   hist     (device) float32 [n_diag, d, d]
+ *   z        (device) float32 [d, d] in/out: initial z if init_uniform == 0,
+ *            otherwise overwritten with the uniform measure on cells j >= i of
+ *            total mass = mean diagram mass; on return, z_t.
+ *   energy   (host)   double out, E_t;  outer (host) int32 out, t
+ * This call synchronises `stream` between outer steps (the stopping test is on
+ * the host).  n_diag >= 1. */
+int pd_barycenter(pdsink_ctx* ctx, int64_t n_diag, const float* hist,
+                  double lambda, int32_t max_outer, double energy_rtol, int32_t init_uniform,
+                  float* z, double* energy, int32_t* outer,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/* k-means assignment step (section 5): the distance of diagram n to centroid
+ * c is the Algorithm 1 cost of (hist[n] + R z_c, z_c + R hist[n]); assign[n]
+ * is the index of the smallest distance, ties to the lowest index.
+ *   hist      (device) float32 [n_diag, d, d]
+ *   centroids (device) float32 [k, d, d]
+ *   assign    (device) int32   [n_diag]      out
+ *   dist      (device) double  [n_diag, k]   out, may be NULL
+ *   status    (device) int32   [n_diag, k]   out, may be NULL
+ *   ws, ws_bytes (device) at least pdsink_workspace_bytes(KMEANS, n_diag * k) */
+int kmeans_assign(pdsink_ctx* ctx, int64_t n_diag, const float* hist,
+                  int32_t k, const float* centroids,
+                  int32_t* assign, double* dist, int32_t* status,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/* Static string for a PDSINK_* return code. */
+const char* pdsink_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PDSINK_H */

@@ -1,0 +1,198 @@
+"""MI355X (gfx950) persistence-diagram Sinkhorn library: Python binding.
+
+Thin marshalling over the C ABI of ``include/pdsink.h`` (loaded with ctypes
+from the in-tree ``libpdsink.so``).  Every step of the computation runs in the
+library's HIP kernels; PyTorch only provides device memory and the current
+stream.  The functions keep the C names:
+
+* ``pd_discretize``       - diagrams (CSR points) to d x d histograms + masses
+* ``sinkhorn_dist_batch`` - Algorithm 1 for a batch of pairs
+* ``pd_barycenter``       - Algorithm 2
+* ``kmeans_assign``       - k-means assignment step
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import PdsinkError  # noqa: F401
+
+__all__ = ["Context", "pd_discretize", "sinkhorn_dist_batch", "pd_barycenter", "kmeans_assign",
+           "PdsinkError", "FP32", "BF16_REFINE"]
+
+FP32 = _lib.PDSINK_FP32
+BF16_REFINE = _lib.PDSINK_BF16_REFINE
+_PREC = {"fp32": FP32, "bf16": BF16_REFINE, "bf16_refine": BF16_REFINE, FP32: FP32, BF16_REFINE: BF16_REFINE}
+
+
+def _vp(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(t, name, dtype, dev):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.device != dev:
+        raise ValueError(f"{name} must be on {dev}, got {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Context:
+    """A ``pdsink_ctx``: grid size, ground exponent, gamma and stopping rule."""
+
+    def __init__(self, d: int, gamma: float, p: float = 2.0, tol: float = 1e-3, max_iter: int = 1000,
+                 precision="fp32", switch_tol: float = 1.5e-3, device=None):
+        lib = _lib.load()
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device_index = int(torch.device("cuda", device).index if not isinstance(device, int) else device)
+        self.device = torch.device("cuda", self.device_index)
+        prm = _lib.Params(int(d), float(p), float(gamma), float(tol), int(max_iter), _PREC[precision],
+                          float(switch_tol))
+        h = ctypes.c_void_p()
+        _lib.check("pdsink_ctx_create", lib.pdsink_ctx_create(ctypes.byref(prm), self.device_index, ctypes.byref(h)))
+        self._h = h
+        self.d, self.gamma, self.p, self.tol, self.max_iter = int(d), float(gamma), float(p), float(tol), int(max_iter)
+        self.precision = _PREC[precision]
+        self.switch_tol = float(switch_tol)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("context closed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.load().pdsink_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def workspace_bytes(self, op: int, n_items: int) -> int:
+        n = ctypes.c_size_t()
+        _lib.check("pdsink_workspace_bytes",
+                   _lib.load().pdsink_workspace_bytes(self.handle, op, int(n_items), ctypes.byref(n)))
+        return int(n.value)
+
+    def workspace(self, op: int, n_items: int) -> torch.Tensor:
+        return torch.empty(max(self.workspace_bytes(op, n_items), 1), dtype=torch.uint8, device=self.device)
+
+
+def pd_discretize(ctx: Context, pts: torch.Tensor, offsets: torch.Tensor, hist=None, mass=None, n_bad=None):
+    """Histograms [n, d, d] (float32) and masses [n] (float64) of CSR diagrams.
+
+    Returns ``(hist, mass, n_bad)``; ``n_bad`` is a device int32 [1] counter of
+    rejected points (added to when given)."""
+    dev = ctx.device
+    _need(pts, "pts", torch.float32, dev)
+    _need(offsets, "offsets", torch.int64, dev)
+    n = offsets.numel() - 1
+    if n < 0:
+        raise ValueError("offsets needs at least one entry")
+    d = ctx.d
+    hist = torch.empty((n, d, d), dtype=torch.float32, device=dev) if hist is None else hist
+    mass = torch.empty((n,), dtype=torch.float64, device=dev) if mass is None else mass
+    n_bad = torch.zeros((1,), dtype=torch.int32, device=dev) if n_bad is None else n_bad
+    _need(hist, "hist", torch.float32, dev)
+    _need(mass, "mass", torch.float64, dev)
+    _need(n_bad, "n_bad", torch.int32, dev)
+    if hist.numel() < n * d * d or mass.numel() < n:
+        raise ValueError("output too small")
+    _lib.check("pd_discretize", _lib.load().pd_discretize(ctx.handle, _vp(pts), _vp(offsets), n, _vp(hist),
+                                                          _vp(mass), _vp(n_bad), _stream()))
+    return hist, mass, n_bad
+
+
+@dataclass
+class DistResult:
+    cost: torch.Tensor      # float64 [n]
+    iters: torch.Tensor     # int32 [n, 2]: BF16 iterations, FP32 iterations
+    err: torch.Tensor       # float32 [n]
+    status: torch.Tensor    # int32 [n]
+
+
+def sinkhorn_dist_batch(ctx: Context, hist_a: torch.Tensor, hist_b: torch.Tensor, ia: torch.Tensor,
+                        ib: torch.Tensor, out: DistResult | None = None, ws: torch.Tensor | None = None) -> DistResult:
+    """Algorithm 1 on pairs (hist_a[ia[q]], hist_b[ib[q]])."""
+    dev = ctx.device
+    for t, nm in ((hist_a, "hist_a"), (hist_b, "hist_b")):
+        _need(t, nm, torch.float32, dev)
+        if t.dim() != 3 or t.shape[1:] != (ctx.d, ctx.d):
+            raise ValueError(f"{nm} must be [n, {ctx.d}, {ctx.d}]")
+    _need(ia, "ia", torch.int32, dev)
+    _need(ib, "ib", torch.int32, dev)
+    n = ia.numel()
+    if ib.numel() != n:
+        raise ValueError("ia and ib differ in length")
+    if n and (int(ia.min()) < 0 or int(ia.max()) >= hist_a.shape[0]
+              or int(ib.min()) < 0 or int(ib.max()) >= hist_b.shape[0]):
+        raise IndexError("pair index out of range")
+    if out is None:
+        out = DistResult(torch.empty(n, dtype=torch.float64, device=dev),
+                         torch.empty((n, 2), dtype=torch.int32, device=dev),
+                         torch.empty(n, dtype=torch.float32, device=dev),
+                         torch.empty(n, dtype=torch.int32, device=dev))
+    if ws is None:
+        ws = ctx.workspace(_lib.PDSINK_OP_DIST, n)
+    _lib.check("sinkhorn_dist_batch", _lib.load().sinkhorn_dist_batch(
+        ctx.handle, n, _vp(hist_a), _vp(hist_b), _vp(ia), _vp(ib), _vp(out.cost), _vp(out.iters),
+        _vp(out.err), _vp(out.status), _vp(ws), ws.numel(), _stream()))
+    return out
+
+
+def kmeans_assign(ctx: Context, hist: torch.Tensor, centroids: torch.Tensor, ws: torch.Tensor | None = None):
+    """Assignment step: returns ``(assign int32 [n], dist float64 [n, k], status int32 [n, k])``."""
+    dev = ctx.device
+    _need(hist, "hist", torch.float32, dev)
+    _need(centroids, "centroids", torch.float32, dev)
+    n, k = hist.shape[0], centroids.shape[0]
+    assign = torch.empty(n, dtype=torch.int32, device=dev)
+    dist = torch.empty((n, k), dtype=torch.float64, device=dev)
+    status = torch.empty((n, k), dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = ctx.workspace(_lib.PDSINK_OP_KMEANS, n * k)
+    _lib.check("kmeans_assign", _lib.load().kmeans_assign(
+        ctx.handle, n, _vp(hist), k, _vp(centroids), _vp(assign), _vp(dist), _vp(status), _vp(ws), ws.numel(),
+        _stream()))
+    return assign, dist, status
+
+
+def pd_barycenter(ctx: Context, hist: torch.Tensor, lam: float = 5.0, max_outer: int = 50,
+                  energy_rtol: float = 0.01, z: torch.Tensor | None = None, ws: torch.Tensor | None = None):
+    """Algorithm 2: returns ``(z [d, d] float32, energy float, outer steps int)``."""
+    dev = ctx.device
+    _need(hist, "hist", torch.float32, dev)
+    n = hist.shape[0]
+    init = z is None
+    if z is None:
+        z = torch.empty((ctx.d, ctx.d), dtype=torch.float32, device=dev)
+    _need(z, "z", torch.float32, dev)
+    if ws is None:
+        ws = ctx.workspace(_lib.PDSINK_OP_BARYCENTER, n)
+    energy = ctypes.c_double()
+    outer = ctypes.c_int32()
+    _lib.check("pd_barycenter", _lib.load().pd_barycenter(
+        ctx.handle, n, _vp(hist), float(lam), int(max_outer), float(energy_rtol), int(init), _vp(z),
+        ctypes.byref(energy), ctypes.byref(outer), _vp(ws), ws.numel(), _stream()))
+    return z, float(energy.value), int(outer.value)

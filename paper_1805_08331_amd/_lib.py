@@ -1,0 +1,98 @@
+"""ctypes declarations of the C ABI in include/pdsink.h.
+
+Loading fails loudly when ``libpdsink.so`` has not been built: there is no
+CPU fallback anywhere in this package.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpdsink.so")
+
+c_int = ctypes.c_int
+c_i32 = ctypes.c_int32
+c_i64 = ctypes.c_int64
+c_dbl = ctypes.c_double
+c_size = ctypes.c_size_t
+c_vp = ctypes.c_void_p
+c_char_p = ctypes.c_char_p
+
+
+class Params(ctypes.Structure):
+    """Mirror of ``pdsink_params``."""
+    _fields_ = [
+        ("d", c_i32),
+        ("p", c_dbl),
+        ("gamma", c_dbl),
+        ("tol", c_dbl),
+        ("max_iter", c_i32),
+        ("precision", c_i32),
+        ("switch_tol", c_dbl),
+    ]
+
+
+PDSINK_OK = 0
+PDSINK_EINVAL = -1
+PDSINK_ENOMEM = -2
+PDSINK_EDEVICE = -3
+PDSINK_ERANGE = -4
+
+PDSINK_FP32 = 0
+PDSINK_BF16_REFINE = 1
+
+PDSINK_ST_MAX_ITER = 1
+PDSINK_ST_NONFINITE = 2
+PDSINK_ST_RANGE = 4
+
+PDSINK_OP_DIST = 0
+PDSINK_OP_KMEANS = 1
+PDSINK_OP_BARYCENTER = 2
+
+# name -> (restype, argtypes); every function declared in include/pdsink.h
+SIGNATURES = {
+    "pdsink_ctx_create": (c_int, [ctypes.POINTER(Params), c_int, ctypes.POINTER(c_vp)]),
+    "pdsink_ctx_destroy": (None, [c_vp]),
+    "pdsink_ctx_params": (c_int, [c_vp, ctypes.POINTER(Params)]),
+    "pdsink_workspace_bytes": (c_int, [c_vp, c_int, c_i64, ctypes.POINTER(c_size)]),
+    "pd_discretize": (c_int, [c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp]),
+    "sinkhorn_dist_batch": (c_int, [c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
+                                    c_vp, c_size, c_vp]),
+    "pd_barycenter": (c_int, [c_vp, c_i64, c_vp, c_dbl, c_i32, c_dbl, c_i32, c_vp,
+                              ctypes.POINTER(c_dbl), ctypes.POINTER(c_i32), c_vp, c_size, c_vp]),
+    "kmeans_assign": (c_int, [c_vp, c_i64, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_size, c_vp]),
+    "pdsink_strerror": (c_char_p, [c_int]),
+}
+
+_LIB = None
+
+
+def load():
+    """Load libpdsink.so (once) and declare every exported function."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_1805_08331_amd.build` "
+            "(hipcc, gfx950). There is no CPU fallback.")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+class PdsinkError(RuntimeError):
+    def __init__(self, fn: str, code: int):
+        msg = load().pdsink_strerror(code).decode()
+        super().__init__(f"{fn} failed: {msg} ({code})")
+        self.code = code
+
+
+def check(fn: str, code: int):
+    if code != PDSINK_OK:
+        raise PdsinkError(fn, code)

@@ -1,0 +1,201 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Same-schedule parity (FP32 contractions): the oracle runs exactly the
+iteration count the GPU reports, from the same start, and the Sinkhorn costs
+agree to 1e-5 relative.  BF16 contractions with FP32 refinement are compared
+with the converged oracle (the fixed point is unique) to 1e-3 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import pdgen
+from oracle import ground, kmeans, sinkhorn
+
+pytestmark = pytest.mark.gpu
+
+FP32_RTOL = 1e-5
+BF16_RTOL = 1e-3
+
+_C = {}
+
+
+def dense_C(d):
+    if d not in _C:
+        _C[d] = ground.dense_cost(d)
+    return _C[d]
+
+
+@pytest.fixture(scope="module")
+def pds():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1805_08331_amd as m
+    return m
+
+
+def run_pairs(pds, ctx, D1s, D2s):
+    dev = ctx.device
+    pts, off = pdgen.to_csr(list(D1s) + list(D2s))
+    hist, mass, bad = pds.pd_discretize(ctx, torch.from_numpy(pts).to(dev), torch.from_numpy(off).to(dev))
+    n = len(D1s)
+    ia = torch.arange(0, n, dtype=torch.int32, device=dev)
+    ib = torch.arange(n, 2 * n, dtype=torch.int32, device=dev)
+    r = pds.sinkhorn_dist_batch(ctx, hist, hist, ia, ib)
+    torch.cuda.synchronize()
+    assert int(bad.item()) == 0
+    return (r.cost.cpu().numpy(), r.iters.cpu().numpy(), r.err.cpu().numpy(), r.status.cpu().numpy(),
+            hist.cpu().numpy())
+
+
+def rel(a, b, m=1.0):
+    return abs(a - b) / max(abs(b), 1e-12 * m)
+
+
+def test_discretize_bit_exact(pds):
+    """Histogram counts equal the oracle's floor(x d) cells, boundaries included."""
+    rng = np.random.default_rng(0)
+    diags = pdgen.pairs_batch(5, 6, 0, 300)[0]
+    edge = np.array([[0.0, 0.0], [1.0, 1.0], [0.5, 0.5], [np.nextafter(np.float32(0.5), np.float32(0)), 0.5],
+                     [0.01, 0.99], [0.0, 1.0]], np.float32)
+    diags = diags + [edge, np.zeros((0, 2), np.float32)]
+    for d in (2, 17, 32, 100, 128):
+        with pds.Context(d, 1e-2) as ctx:
+            pts, off = pdgen.to_csr(diags)
+            hist, mass, bad = pds.pd_discretize(ctx, torch.from_numpy(pts).cuda(), torch.from_numpy(off).cuda())
+            h = hist.cpu().numpy()
+            for q, D in enumerate(diags):
+                np.testing.assert_array_equal(h[q], ground.discretize(D, d))
+                assert mass[q].item() == len(D)
+            assert bad.item() == 0
+    # invalid points are skipped and counted
+    badpts = np.array([[0.6, 0.5], [-0.1, 0.2], [0.2, 1.5], [np.nan, 0.3], [0.1, 0.2]], np.float32)
+    with pds.Context(8, 1e-2) as ctx:
+        pts, off = pdgen.to_csr([badpts])
+        hist, mass, bad = pds.pd_discretize(ctx, torch.from_numpy(pts).cuda(), torch.from_numpy(off).cuda())
+        assert bad.item() == 4 and mass.item() == 1 and hist.sum().item() == 1
+
+
+def test_config1_single_pair(pds):
+    """d=32, gamma=1e-2, 300 iterations, 20 and 30 points (seed 0)."""
+    D1, D2 = pdgen.pair_single(0)
+    d, g = 32, 1e-2
+    with pds.Context(d, g, tol=0.0, max_iter=300) as ctx:
+        cost, iters, err, st, _ = run_pairs(pds, ctx, [D1], [D2])
+    r = sinkhorn.sinkhorn(ground.discretize(D1, d), ground.discretize(D2, d), g, max_iter=300, C=dense_C(d))
+    assert iters[0].tolist() == [0, 300]
+    assert rel(cost[0], r.cost) <= FP32_RTOL
+    assert st[0] & ~1 == 0
+
+
+@pytest.mark.parametrize("d,g,lo,hi", [(32, 5e-3, 5, 80), (50, 1e-3, 20, 150), (64, 2e-3, 1, 60)])
+def test_batch_same_schedule(pds, d, g, lo, hi):
+    """Small batches spanning several 32x32 tiles with a ragged tail."""
+    D1s, D2s = pdgen.pairs_batch(d, 12, lo, hi)
+    with pds.Context(d, g, tol=1e-4, max_iter=3000) as ctx:
+        cost, iters, err, st, hist = run_pairs(pds, ctx, D1s, D2s)
+    C = dense_C(d)
+    for q in range(len(D1s)):
+        t = int(iters[q].sum())
+        r = sinkhorn.sinkhorn(hist[q], hist[len(D1s) + q], g, max_iter=t, C=C)
+        assert rel(cost[q], r.cost) <= FP32_RTOL, (q, cost[q], r.cost)
+        assert err[q] <= 1e-4 and st[q] == 0
+        assert math.isclose(err[q], r.err, rel_tol=1e-3, abs_tol=1e-7)
+        # the FP64 run crosses the tolerance at the same iteration (or one off at the boundary)
+        ro = sinkhorn.sinkhorn(hist[q], hist[len(D1s) + q], g, tol=1e-4, max_iter=3000, C=C)
+        assert abs(ro.iters - t) <= 1
+
+
+def test_config2_sampled_full_batch(pds):
+    """1024 pairs at d=100, gamma=1e-3, tol=1e-3 (the benchmark's launch); three
+    pairs re-run by the oracle at the GPU's iteration counts."""
+    d, g = 100, 1e-3
+    D1s, D2s = pdgen.pairs_batch(0, 1024)
+    with pds.Context(d, g, tol=1e-3, max_iter=5000) as ctx:
+        cost, iters, err, st, hist = run_pairs(pds, ctx, D1s, D2s)
+    assert np.all(st == 0) and np.all(err <= 1e-3)
+    assert np.all(iters[:, 0] == 0)
+    assert iters[:3, 1].tolist() == [157, 495, 348]      # FP64 oracle counts for pairs 0, 1, 2
+    C = dense_C(d)
+    for q in (0, 1, 777):
+        r = sinkhorn.sinkhorn(hist[q], hist[1024 + q], g, max_iter=int(iters[q, 1]), C=C)
+        assert rel(cost[q], r.cost) <= FP32_RTOL, (q, cost[q], r.cost)
+
+
+def test_bf16_refine_against_converged(pds):
+    """BF16 contractions then FP32 refinement to 1e-5 match the converged FP64
+    fixed point to 1e-3 relative cost."""
+    d, g = 50, 1e-3
+    D1s, D2s = pdgen.pairs_batch(3, 3, 20, 200)
+    with pds.Context(d, g, tol=1e-5, max_iter=20000, precision="bf16", switch_tol=1.5e-3) as ctx:
+        cost, iters, err, st, hist = run_pairs(pds, ctx, D1s, D2s)
+    C = dense_C(d)
+    assert np.all(iters[:, 0] > 0) and np.all(st == 0)
+    for q in range(len(D1s)):
+        r = sinkhorn.sinkhorn(hist[q], hist[len(D1s) + q], g, tol=1e-7, max_iter=100000, C=C)
+        assert rel(cost[q], r.cost) <= BF16_RTOL, (q, cost[q], r.cost)
+
+
+def test_edge_cases(pds):
+    """Empty diagrams (closed form: all mass to the diagonal), identical
+    diagrams, single points, points on the border, d = 2 and d = 128."""
+    rng = np.random.default_rng(2)
+    empty = np.zeros((0, 2), np.float32)
+    one = np.array([[0.25, 0.75]], np.float32)
+    border = np.array([[0.0, 1.0], [1.0, 1.0], [0.0, 0.0]], np.float32)
+    D = pdgen.gen(rng, 40)
+    cases = [(D, empty), (empty, D), (empty, empty), (D, D), (one, one), (one, border), (border, D)]
+    for d, g in ((2, 0.5), (32, 1e-2), (100, 1e-3), (128, 1e-3)):
+        with pds.Context(d, g, tol=1e-6, max_iter=4000) as ctx:
+            cost, iters, err, st, hist = run_pairs(pds, ctx, [c[0] for c in cases], [c[1] for c in cases])
+        n = len(cases)
+        h0 = ground.discretize(D, d)
+        closed = float(np.sum(h0 * ground.cost_diag(d)))
+        assert rel(cost[0], closed) <= FP32_RTOL and rel(cost[1], closed) <= FP32_RTOL
+        assert cost[2] == 0.0 and iters[2].sum() == 0 and st[2] == 0
+        C = dense_C(d) if d <= 32 else None
+        for q in range(3, n):
+            assert st[q] & ~1 == 0, (d, q, st[q])          # never non-finite or out of range
+            if C is not None:
+                # degenerate pairs (one point each) converge slowly: the status must
+                # agree with the FP64 run, and the costs at the same iteration count
+                r = sinkhorn.sinkhorn(hist[q], hist[n + q], g, tol=1e-6, max_iter=4000, C=C)
+                assert (st[q] == 1) == (r.err > 1e-6), (d, q, st[q], r.err)
+                r = sinkhorn.sinkhorn(hist[q], hist[n + q], g, max_iter=int(iters[q].sum()), C=C)
+                assert rel(cost[q], r.cost, m=1.0) <= FP32_RTOL or abs(cost[q] - r.cost) < 1e-9, (d, q)
+
+
+def test_alone_equals_in_batch(pds):
+    """A pair's result does not depend on the batch it runs in (bitwise)."""
+    d, g = 64, 2e-3
+    D1s, D2s = pdgen.pairs_batch(9, 20, 5, 200)
+    with pds.Context(d, g, tol=1e-4, max_iter=3000, precision="bf16") as ctx:
+        cost, iters, err, st, _ = run_pairs(pds, ctx, D1s, D2s)
+        for q in (0, 7, 19):
+            c1, i1, e1, s1, _ = run_pairs(pds, ctx, [D1s[q]], [D2s[q]])
+            assert c1[0] == cost[q] and np.array_equal(i1[0], iters[q]) and e1[0] == err[q]
+
+
+def test_kmeans_assign_matches_oracle(pds):
+    d, g = 32, 5e-3
+    diags, labels = pdgen.kmeans_set(4, 24, n_templates=3, template_size=30)
+    hists = [ground.discretize(x, d) for x in diags]
+    cents = [hists[0], hists[1], hists[2]]
+    ol, odist, oit = kmeans.assign(hists, cents, g, tol=1e-4, max_iter=5000, C=dense_C(d))
+    with pds.Context(d, g, tol=1e-4, max_iter=5000) as ctx:
+        H = torch.from_numpy(np.stack(hists).astype(np.float32)).cuda()
+        Cn = torch.from_numpy(np.stack(cents).astype(np.float32)).cuda()
+        assign, dist, st = pds.kmeans_assign(ctx, H, Cn)
+        torch.cuda.synchronize()
+    dist = dist.cpu().numpy()
+    assign = assign.cpu().numpy()
+    assert np.all(st.cpu().numpy() == 0)
+    np.testing.assert_allclose(dist, odist, rtol=2e-3)      # stopping iterations may differ by one
+    for n in range(len(hists)):
+        srt = np.sort(odist[n])
+        if srt[1] - srt[0] > 1e-2 * srt[0]:
+            assert assign[n] == ol[n]
+        else:
+            assert dist[n, assign[n]] <= dist[n].min() * (1 + 1e-12)
