@@ -1,0 +1,217 @@
+"""Benchmark: batched PD-pair Sinkhorn iterations per second at d=100.
+
+Workload (one "step"): 1024 pairs of synthetic diagrams (50..500 points each,
+birth ~ U[0,1), death = min(birth + Exp(0.2), 1), seed 0), discretised on the
+100 x 100 grid plus the diagonal bin, then Algorithm 1 with gamma = 1e-3 until
+the marginal L1 error / mass <= 1e-3, and the Sinkhorn cost of Proposition 3.
+Points are resident on the GPU before timing starts.
+
+``value`` is pair-iterations per second of the BF16-contraction path with FP32
+refinement (every executed iteration counted, BF16 and FP32); the FP32 path on
+the same workload is reported beside it.  Kernel durations come from HIP events
+on the launch stream; the roofline uses algorithmic flops (8 d^3 per
+pair-iteration: two K applications of two d x d x d contractions each, plus
+the final error-check application and the four cost contractions per pair).
+
+The CPU baseline times the FP64 oracle (dense (d^2+1)-point Sinkhorn) on a
+bounded sample of the same pairs.  Only one GPU is used.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_BF16 = 2.5e15      # MI355X dense BF16 MFMA, FLOP/s
+PEAK_FP32 = 157.3e12    # MI355X FP32 (matrix and vector), FLOP/s
+PEAK_HBM = 8.0e12       # B/s
+
+D, GAMMA, TOL, NPAIRS = 100, 1e-3, 1e-3, 1024
+
+
+def flops_of(iters_total: int, n_pairs: int, d: int = D) -> float:
+    """Algorithmic flops of one launch: 8 d^3 per pair-iteration, 4 d^3 for the
+    last error-check K application and 8 d^3 for the cost, per pair."""
+    return 8.0 * d ** 3 * iters_total + 12.0 * d ** 3 * n_pairs
+
+
+def run_gpu(precision: str, steps: int, warmup: int, pts_d, off_d, switch_tol: float):
+    import torch
+    import paper_1805_08331_amd as pds
+
+    ctx = pds.Context(D, GAMMA, tol=TOL, max_iter=5000, precision=precision, switch_tol=switch_tol)
+    dev = ctx.device
+    n = NPAIRS
+    hist = torch.empty((2 * n, D, D), dtype=torch.float32, device=dev)
+    mass = torch.empty((2 * n,), dtype=torch.float64, device=dev)
+    nbad = torch.zeros((1,), dtype=torch.int32, device=dev)
+    ia = torch.arange(0, n, dtype=torch.int32, device=dev)
+    ib = torch.arange(n, 2 * n, dtype=torch.int32, device=dev)
+    out = pds.DistResult(torch.empty(n, dtype=torch.float64, device=dev),
+                         torch.empty((n, 2), dtype=torch.int32, device=dev),
+                         torch.empty(n, dtype=torch.float32, device=dev),
+                         torch.empty(n, dtype=torch.int32, device=dev))
+    ws = ctx.workspace(pds._lib.PDSINK_OP_DIST, n)
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+
+    def step(i=None):
+        pds.pd_discretize(ctx, pts_d, off_d, hist, mass, nbad)
+        if i is not None:
+            ev[i][0].record(stream)
+        pds.sinkhorn_dist_batch(ctx, hist, hist, ia, ib, out=out, ws=ws)
+        if i is not None:
+            ev[i][1].record(stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step_ms = []
+    for i in range(steps):
+        s0 = time.perf_counter()
+        step(i)
+        torch.cuda.synchronize()
+        step_ms.append((time.perf_counter() - s0) * 1e3)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = [a.elapsed_time(b) for a, b in ev]
+    iters = out.iters.cpu().numpy().astype(np.int64)
+    status = out.status.cpu().numpy()
+    err = out.err.cpu().numpy()
+    ctx.close()
+    it_total = int(iters.sum())
+    return {
+        "wall_s": wall,
+        "step_ms": step_ms,
+        "kernel_ms": kern_ms,
+        "iters_total": it_total,
+        "iters_bf16": int(iters[:, 0].sum()),
+        "iters_fp32": int(iters[:, 1].sum()),
+        "n_bad_status": int((status != 0).sum()),
+        "max_err": float(err.max()),
+    }
+
+
+def cpu_baseline(budget_s: float = 20.0):
+    """FP64 oracle on config-2 pairs 0, 1, ... until ~budget_s of CPU work."""
+    import pdgen
+    from oracle import ground, sinkhorn
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([x.get("num_threads", 1) for x in threadpool_info()] or [1])
+    except Exception:
+        blas_threads = os.cpu_count() or 1
+    d1, d2 = pdgen.pairs_batch(0, 16)
+    C = ground.dense_cost(D)
+    its, t_used, done = 0, 0.0, 0
+    for q in range(16):
+        h1, h2 = ground.discretize(d1[q], D), ground.discretize(d2[q], D)
+        t0 = time.perf_counter()
+        r = sinkhorn.sinkhorn(h1, h2, GAMMA, tol=TOL, max_iter=5000, C=C)
+        t_used += time.perf_counter() - t0
+        its += r.iters
+        done += 1
+        if t_used >= budget_s:
+            break
+    return {"value": its / t_used, "unit": "pair-it/s", "cores": int(blas_threads), "kind": "oracle",
+            "sample": f"config-2 pairs 0..{done - 1} ({its} pair-iterations, {t_used:.1f} s), FP64 dense "
+                      f"(d^2+1)-point kernel on the host, cost matrix built once outside the timing; "
+                      f"os.cpu_count()={os.cpu_count()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--only", choices=["bf16", "fp32"], default=None, help="run one precision only")
+    ap.add_argument("--switch-tol", type=float, default=1.5e-3)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the per-GPU shard is the batch measured at --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import pdgen
+
+    d1, d2 = pdgen.pairs_batch(0, NPAIRS)
+    pts, off = pdgen.to_csr(d1 + d2)
+    pts_d = torch.from_numpy(pts).cuda()
+    off_d = torch.from_numpy(off).cuda()
+
+    res = {}
+    for prec in (["bf16", "fp32"] if args.only is None else [args.only]):
+        r = run_gpu(prec, args.steps, args.warmup, pts_d, off_d, args.switch_tol)
+        k_avg = float(np.mean(r["kernel_ms"])) / 1e3
+        fl = flops_of(r["iters_total"], NPAIRS)
+        r["pair_it_per_s"] = r["iters_total"] * args.steps / r["wall_s"]
+        r["kernel_pair_it_per_s"] = r["iters_total"] / k_avg
+        r["pairs_per_s"] = NPAIRS * args.steps / r["wall_s"]
+        r["achieved_tflops"] = fl / k_avg / 1e12
+        if prec == "bf16":
+            # minimum time at peak for this mix of BF16 and FP32 iterations
+            f_b = 8.0 * D ** 3 * r["iters_bf16"]
+            f_f = fl - f_b
+            peak = fl / (f_b / PEAK_BF16 + f_f / PEAK_FP32)
+        else:
+            peak = PEAK_FP32
+        r["peak_tflops"] = peak / 1e12
+        res[prec] = r
+        print(f"[{prec}] {r['iters_total']} pair-iterations per step, kernel {k_avg * 1e3:.2f} ms, "
+              f"{r['kernel_pair_it_per_s']:.3e} pair-it/s, {r['achieved_tflops']:.1f} TFLOP/s, "
+              f"bad status {r['n_bad_status']}", file=sys.stderr, flush=True)
+
+    main_key = "bf16" if "bf16" in res else "fp32"
+    m = res[main_key]
+    k_avg = float(np.mean(m["kernel_ms"])) / 1e3
+    out = {
+        "metric": "PD-pair Sinkhorn iters/sec at d=100, bf16 vs fp32 @1e-3 err; p50/p99 latency",
+        "value": m["pair_it_per_s"],
+        "unit": "pair-it/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": m["wall_s"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16" if main_key == "bf16" else "fp32",
+        "data": "synthetic",
+        "config": {"workload": "batched distances: 1024 PD pairs, 50-500 points, d=100 grid + diagonal bin, "
+                               "gamma=1e-3, stop at marginal L1 error 1e-3",
+                   "pairs": NPAIRS, "d": D, "gamma": GAMMA, "tol": TOL,
+                   "precision": "bf16 contractions, fp32 refinement" if main_key == "bf16" else "fp32",
+                   "switch_tol": args.switch_tol},
+        "pairs_per_s": m["pairs_per_s"],
+        "pair_iters_per_step": m["iters_total"],
+        "latency_ms": {"p50": float(np.percentile(m["step_ms"], 50)), "p99": float(np.percentile(m["step_ms"], 99)),
+                       "of": "one 1024-pair batch (discretise + Algorithm 1 + cost)"},
+        "roofline": {"bound": "mfma", "achieved": m["achieved_tflops"], "peak": m["peak_tflops"], "unit": "TFLOP/s",
+                     "frac": m["achieved_tflops"] / m["peak_tflops"], "traffic": None,
+                     "kernel": "sinkhorn_pair_kernel<128>", "kernel_ms": k_avg * 1e3},
+    }
+    if "fp32" in res and main_key == "bf16":
+        f = res["fp32"]
+        out["fp32"] = {"value": f["pair_it_per_s"], "unit": "pair-it/s", "pair_iters_per_step": f["iters_total"],
+                       "kernel_ms": float(np.mean(f["kernel_ms"])), "achieved_tflops": f["achieved_tflops"],
+                       "frac_of_fp32_peak": f["achieved_tflops"] / f["peak_tflops"], "pairs_per_s": f["pairs_per_s"]}
+        out["bf16_over_fp32"] = m["pair_it_per_s"] / f["pair_it_per_s"]
+        out["bf16_iterations"] = {"bf16": m["iters_bf16"], "fp32_refine": m["iters_fp32"]}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -89,7 +89,7 @@ __global__ __launch_bounds__(WG) void discretize_kernel(const float* __restrict_
 
 template <int D>
 int launch_pairs(const pdsink_ctx* ctx, const PairParams& pp, hipStream_t st) {
-  hipLaunchKernelGGL(sinkhorn_pair_kernel<D>, dim3((unsigned)pp.n_pairs), dim3(WG), 0, st, pp);
+  hipLaunchKernelGGL(sinkhorn_pair_kernel<D>, dim3((unsigned)pp.n_pairs), dim3(Cfg<D>::WGS), 0, st, pp);
   return last_error();
 }
 

@@ -55,25 +55,27 @@ __device__ __forceinline__ int wave_min(int v) {
   return v;
 }
 
-// Sum over the workgroup, same fixed order on every call (deterministic).
+// Sum over a workgroup of NW waves, same fixed order on every call (deterministic).
+template <int NW = NWAVE>
 __device__ __forceinline__ double block_sum(double v, double* red) {
   v = wave_sum(v);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   double t = 0.0;
-#pragma unroll
-  for (int w = 0; w < NWAVE; ++w) t += red[w];
+#pragma unroll 4
+  for (int w = 0; w < NW; ++w) t += red[w];
   return t;
 }
+template <int NW = NWAVE>
 __device__ __forceinline__ int block_max(int v, int* red) {
   v = wave_max(v);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   int t = red[0];
-#pragma unroll
-  for (int w = 1; w < NWAVE; ++w) t = max(t, red[w]);
+#pragma unroll 4
+  for (int w = 1; w < NW; ++w) t = max(t, red[w]);
   return t;
 }
 
@@ -97,6 +99,7 @@ __device__ __forceinline__ ESum wave_esum(ESum v) {
   }
   return v;
 }
+template <int NW = NWAVE>
 __device__ __forceinline__ ESum block_esum(ESum v, int* rede, double* reds) {
   v = wave_esum(v);
   __syncthreads();
@@ -106,8 +109,8 @@ __device__ __forceinline__ ESum block_esum(ESum v, int* rede, double* reds) {
   }
   __syncthreads();
   ESum t{rede[0], reds[0]};
-#pragma unroll
-  for (int w = 1; w < NWAVE; ++w) t = esum_add(t, ESum{rede[w], reds[w]});
+#pragma unroll 2
+  for (int w = 1; w < NW; ++w) t = esum_add(t, ESum{rede[w], reds[w]});
   return t;
 }
 
