@@ -98,6 +98,7 @@ def run_gpu(precision: str, steps: int, warmup: int, pts_d, off_d, switch_tol: f
         "iters_fp32": int(iters[:, 1].sum()),
         "n_bad_status": int((status != 0).sum()),
         "max_err": float(err.max()),
+        "iters_per_pair": iters.sum(axis=1),
     }
 
 
@@ -168,9 +169,13 @@ def main():
             peak = PEAK_FP32
         r["peak_tflops"] = peak / 1e12
         res[prec] = r
+        ipp = r.pop("iters_per_pair")
+        r["iters_quantiles"] = {"p50": int(np.percentile(ipp, 50)), "p99": int(np.percentile(ipp, 99)),
+                                "max": int(ipp.max())}
         print(f"[{prec}] {r['iters_total']} pair-iterations per step, kernel {k_avg * 1e3:.2f} ms, "
               f"{r['kernel_pair_it_per_s']:.3e} pair-it/s, {r['achieved_tflops']:.1f} TFLOP/s, "
-              f"bad status {r['n_bad_status']}", file=sys.stderr, flush=True)
+              f"bad status {r['n_bad_status']}, iterations per pair {r['iters_quantiles']}",
+              file=sys.stderr, flush=True)
 
     main_key = "bf16" if "bf16" in res else "fp32"
     m = res[main_key]
@@ -199,7 +204,7 @@ def main():
                        "of": "one 1024-pair batch (discretise + Algorithm 1 + cost)"},
         "roofline": {"bound": "mfma", "achieved": m["achieved_tflops"], "peak": m["peak_tflops"], "unit": "TFLOP/s",
                      "frac": m["achieved_tflops"] / m["peak_tflops"], "traffic": None,
-                     "kernel": "sinkhorn_pair_kernel<128>", "kernel_ms": k_avg * 1e3},
+                     "kernel": "sinkhorn_pair_kernel<128, 1>", "kernel_ms": k_avg * 1e3},
     }
     if "fp32" in res and main_key == "bf16":
         f = res["fp32"]
@@ -208,6 +213,7 @@ def main():
                        "frac_of_fp32_peak": f["achieved_tflops"] / f["peak_tflops"], "pairs_per_s": f["pairs_per_s"]}
         out["bf16_over_fp32"] = m["pair_it_per_s"] / f["pair_it_per_s"]
         out["bf16_iterations"] = {"bf16": m["iters_bf16"], "fp32_refine": m["iters_fp32"]}
+    out["iterations_per_pair"] = m["iters_quantiles"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

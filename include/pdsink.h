@@ -113,8 +113,11 @@ int pd_discretize(pdsink_ctx* ctx, const float* pts, const int64_t* offsets, int
  *   iters          (device) int32   [n_pairs, 2] out: iterations in BF16, in FP32
  *   err            (device) float   [n_pairs]  out: marginal error / m at stopping
  *   status         (device) int32   [n_pairs]  out: PDSINK_ST_* bits
- *   ws, ws_bytes   (device) workspace of at least pdsink_workspace_bytes(DIST)
- * Masses are the histogram sums.  n_pairs = 0 is a no-op. */
+ *   ws, ws_bytes   (device) workspace of at least pdsink_workspace_bytes(DIST, n_pairs)
+ *                  bytes (one routing byte per pair); PDSINK_ENOMEM if smaller
+ * Masses are the histogram sums.  n_pairs = 0 is a no-op.  Any support size
+ * is accepted: pairs whose supports exceed the compact kernel's lists run in a
+ * dense kernel, from the same launch sequence. */
 int sinkhorn_dist_batch(pdsink_ctx* ctx, int64_t n_pairs,
                         const float* hist_a, const float* hist_b,
                         const int32_t* ia, const int32_t* ib,

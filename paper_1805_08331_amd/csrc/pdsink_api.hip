@@ -11,9 +11,12 @@
 
 #include "../../include/pdsink.h"
 #include "pdsink_device.h"
+#include "sinkhorn_dense.h"
 #include "sinkhorn_pair.h"
 
 using namespace pdsink;
+
+
 
 struct pdsink_ctx {
   pdsink_params prm;
@@ -51,6 +54,8 @@ void split_pow2(double g, int* e, float* m) {
   *m = (float)std::exp2(g - c);
 }
 
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
 int last_error() { return hipGetLastError() == hipSuccess ? PDSINK_OK : PDSINK_EDEVICE; }
 
 __global__ __launch_bounds__(WG) void discretize_kernel(const float* __restrict__ pts, const int64_t* __restrict__ off,
@@ -87,14 +92,38 @@ __global__ __launch_bounds__(WG) void discretize_kernel(const float* __restrict_
   if (threadIdx.x == 0) mass[n] = kept;
 }
 
-template <int D>
-int launch_pairs(const pdsink_ctx* ctx, const PairParams& pp, hipStream_t st) {
-  hipLaunchKernelGGL(sinkhorn_pair_kernel<D>, dim3((unsigned)pp.n_pairs), dim3(Cfg<D>::WGS), 0, st, pp);
+template <int D, int SPT>
+int launch_pairs(PairParams pp, int level, hipStream_t st) {
+  pp.only_redo = level;
+  hipLaunchKernelGGL((sinkhorn_pair_kernel<D, SPT>), dim3((unsigned)pp.n_pairs), dim3(PWGS), 0, st, pp);
   return last_error();
 }
 
+template <int D>
+int launch_dense(PairParams pp, int level, hipStream_t st) {
+  pp.only_redo = level;
+  hipLaunchKernelGGL((dense::sinkhorn_pair_kernel<D>), dim3((unsigned)pp.n_pairs), dim3(dense::Cfg<D>::WGS), 0, st,
+                     pp);
+  return last_error();
+}
+
+// Level 0 runs every pair in the compact kernel with one support entry per
+// thread (supports up to 512 cells per side); pairs that do not fit flag
+// themselves and run again at level 1 with two entries per thread (1024
+// cells), then at level 2 in the dense kernel.  All launches go to the same
+// stream, with no host synchronisation; a level with no flagged pair exits at
+// once.
+template <int D>
+int launch_levels(PairParams pp, hipStream_t st) {
+  int rc = launch_pairs<D, 1>(pp, 0, st);
+  if (!rc) rc = launch_pairs<D, 2>(pp, 1, st);
+  if (!rc) rc = launch_dense<D>(pp, 2, st);
+  return rc;
+}
+
 int run_pairs(const pdsink_ctx* ctx, int64_t n_pairs, const float* ha, const float* hb, const int32_t* ia,
-              const int32_t* ib, double* cost, int32_t* iters, float* err, int32_t* status, hipStream_t st) {
+              const int32_t* ib, double* cost, int32_t* iters, float* err, int32_t* status, unsigned char* redo,
+              hipStream_t st) {
   PairParams pp;
   pp.d = ctx->prm.d;
   pp.tol = ctx->prm.tol;
@@ -116,10 +145,11 @@ int run_pairs(const pdsink_ctx* ctx, int64_t n_pairs, const float* ha, const flo
   pp.iters = iters;
   pp.err = err;
   pp.status = status;
+  pp.redo = redo;
   switch (ctx->D) {
-    case 32: return launch_pairs<32>(ctx, pp, st);
-    case 64: return launch_pairs<64>(ctx, pp, st);
-    default: return launch_pairs<128>(ctx, pp, st);
+    case 32: return launch_levels<32>(pp, st);
+    case 64: return launch_levels<64>(pp, st);
+    default: return launch_levels<128>(pp, st);
   }
 }
 
@@ -149,7 +179,6 @@ __global__ void kmeans_argmin_kernel(int64_t n_diag, int k, const double* __rest
   assign[n] = best;
 }
 
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
@@ -245,9 +274,10 @@ int pdsink_ctx_params(const pdsink_ctx* ctx, pdsink_params* out) {
 int pdsink_workspace_bytes(const pdsink_ctx* ctx, int op, int64_t n_items, size_t* bytes) {
   if (!ctx || !bytes || n_items < 0) return PDSINK_EINVAL;
   switch (op) {
-    case PDSINK_OP_DIST: *bytes = 256; return PDSINK_OK;
-    case PDSINK_OP_KMEANS:   // ia, ib, cost, iters, err, status per pair
-      *bytes = align256(n_items * 4) * 2 + align256(n_items * 8) + align256(n_items * 8) + align256(n_items * 4) * 2;
+    case PDSINK_OP_DIST: *bytes = align256(n_items); return PDSINK_OK;
+    case PDSINK_OP_KMEANS:   // ia, ib, cost, iters, err, status, redo per pair
+      *bytes = align256(n_items * 4) * 2 + align256(n_items * 8) + align256(n_items * 8) + align256(n_items * 4) * 2 +
+               align256(n_items);
       return PDSINK_OK;
     case PDSINK_OP_BARYCENTER: *bytes = 256; return PDSINK_OK;
     default: return PDSINK_EINVAL;
@@ -270,15 +300,17 @@ int pd_discretize(pdsink_ctx* ctx, const float* pts, const int64_t* offsets, int
 int sinkhorn_dist_batch(pdsink_ctx* ctx, int64_t n_pairs, const float* hist_a, const float* hist_b,
                         const int32_t* ia, const int32_t* ib, double* cost, int32_t* iters, float* err,
                         int32_t* status, void* ws, size_t ws_bytes, void* stream) {
-  (void)ws;
-  (void)ws_bytes;
   if (!ctx || n_pairs < 0) return PDSINK_EINVAL;
   if (n_pairs == 0) return PDSINK_OK;
   if (n_pairs > INT_MAX || !hist_a || !hist_b || !ia || !ib || !cost || !iters || !err || !status)
     return PDSINK_EINVAL;
+  size_t need = 0;
+  pdsink_workspace_bytes(ctx, PDSINK_OP_DIST, n_pairs, &need);
+  if (!ws || ws_bytes < need) return PDSINK_ENOMEM;
   DeviceGuard g(ctx->device);
   if (!g.ok) return PDSINK_EDEVICE;
-  return run_pairs(ctx, n_pairs, hist_a, hist_b, ia, ib, cost, iters, err, status, (hipStream_t)stream);
+  return run_pairs(ctx, n_pairs, hist_a, hist_b, ia, ib, cost, iters, err, status, (unsigned char*)ws,
+                   (hipStream_t)stream);
 }
 
 int kmeans_assign(pdsink_ctx* ctx, int64_t n_diag, const float* hist, int32_t k, const float* centroids,
@@ -305,11 +337,13 @@ int kmeans_assign(pdsink_ctx* ctx, int64_t n_diag, const float* hist, int32_t k,
   float* err = (float*)w;
   w += align256(np * 4);
   int32_t* st = (int32_t*)w;
+  w += align256(np * 4);
+  unsigned char* redo = (unsigned char*)w;
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(kmeans_pairs_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, n_diag, k, ia, ib);
   int rc = last_error();
   if (rc) return rc;
-  rc = run_pairs(ctx, np, hist, centroids, ia, ib, cost, iters, err, st, s);
+  rc = run_pairs(ctx, np, hist, centroids, ia, ib, cost, iters, err, st, redo, s);
   if (rc) return rc;
   hipLaunchKernelGGL(kmeans_argmin_kernel, dim3((unsigned)((n_diag + 255) / 256)), dim3(256), 0, s, n_diag, k, cost,
                      assign, dist, st, status);

@@ -1,13 +1,17 @@
 // Fused per-pair Sinkhorn kernel: Algorithm 1 of Lacombe, Cuturi, Oudot
-// (NeurIPS 2018) on the d x d grid plus the diagonal bin.  One workgroup per
-// pair; every iterate stays in LDS and registers for the whole solve.
+// (NeurIPS 2018) on the d x d grid plus the diagonal bin.  One workgroup of
+// 8 waves per pair; every iterate stays in LDS and registers for the whole
+// solve.
 //
 // Work layout.  The grid is padded to D = 32, 64 or 128 and cut into 32 x 32
-// tiles; the workgroup has one wave per tile.  A wave computes its tile of
-// both contractions of Proposition 2 on the matrix cores and owns the 16 grid
-// cells of its accumulator layout (lane l, register r: row 8(r/4) + 4(l/32) +
-// r%4, column l%32 of the tile), so the result of K x is consumed straight
-// from the accumulators by the elementwise update.
+// tiles; wave w computes tiles w, w + 8, ... of both contractions of
+// Proposition 2 on the matrix cores.  Everything elementwise (the scaling
+// update, the marginal error, the diagonal-bin terms, the refit of the
+// scales) runs over compact lists of the two histograms' supports: u is zero
+// off supp(a) and v off supp(b), so only those cells carry state.  Support
+// entry s of a side belongs to thread s mod 512, register slot s / 512.
+// The lists are built once per pair with a block prefix scan (deterministic
+// order), and the contraction result reaches them through one LDS tile store.
 //
 // Numerical representation (the paper is silent on stabilisation).  A scaling
 // vector x on the grid is stored as x_ij = 2^(P_i + Q_j) * xt_ij with integer
@@ -67,21 +71,28 @@ struct PairParams {
   int* iters;
   float* err;
   int* status;
+  // support-size routing between kernel variants: a launch at level L handles
+  // the pairs with redo[q] == L (level 0: every pair, whatever redo holds) and
+  // sets redo[q] = L + 1, leaving the outputs alone, for a pair whose support
+  // does not fit the variant; else it sets redo[q] = L.
+  unsigned char* redo;
+  int only_redo;
 };
 
+constexpr int PWGS = 512;      // threads per pair workgroup
+constexpr int PNW = PWGS / 64; // its waves
 constexpr int MAXSUSP = 256;   // suspects handled per half step
 constexpr int XCHUNK = 4;      // suspects evaluated together
-constexpr int QSUSP = 1 << 28; // per-cell marker: cell is suspect number q - QSUSP
-constexpr int CELLS = 16;      // grid cells per lane (one 32x32 accumulator tile per wave)
+constexpr int QSUSP = 1 << 28; // per-entry marker: entry is suspect number q - QSUSP
 constexpr int HEAD = 40;       // kernel headroom octaves for an input residual within 2^20
 
 template <int D>
 struct Cfg {
-  static constexpr int NT = D / 32;        // tiles per grid dimension
-  static constexpr int NW = NT * NT;       // waves: one output tile each
-  static constexpr int WGS = NW * 64;      // threads per workgroup
-  static constexpr int LDF = D + 1;        // FP32 row stride: rows start in different banks
-  static constexpr int LDB = D + 8;        // BF16 row stride: 16-byte aligned rows
+  static constexpr int NT = D / 32;          // tiles per grid dimension
+  static constexpr int NTILES = NT * NT;     // waves with a contraction tile
+  static constexpr int LDF = D + 1;          // FP32 row stride: rows start in different banks
+  static constexpr int LDB = D + 8;          // BF16 row stride: 16-byte aligned rows
+  static constexpr int TPR = PWGS / (2 * D); // threads per (side, row) in compute_RS
 };
 
 template <int D>
@@ -90,7 +101,7 @@ struct PairSmem {
   union {
     struct {
       float X[D * C::LDF];    // input residual (A operand of contraction 1)
-      float T[D * C::LDF];    // X kt2^T, row-major [k][j]
+      float T[D * C::LDF];    // X kt2^T, row-major [k][j]; then the K x tile store
     } f;
     struct {
       __bf16 X[D * C::LDB];
@@ -98,64 +109,83 @@ struct PairSmem {
       __bf16 K1[D * C::LDB];  // kt1 [i][k]
       __bf16 K2[D * C::LDB];  // kt2 [j][l]
     } b;
+    struct {
+      int cell[D * D];        // support-list staging at pair start
+      float val[D * D];
+    } st;
   } u;
   int tge[2 * D], tgde[2 * D];
   float tgm[2 * D], tgdm[2 * D], tc1[2 * D], tcd[2 * D];
   int Pu[D], Qu[D], Pv[D], Qv[D], R[D], S[D];
   int rmx[D], rmn[D], cmx[D], cmn[D], rho[D], sig[D];
-  double red[C::NW];
-  double reds[C::NW];
-  int rede[C::NW];
-  int redi[C::NW];
+  double red[PNW];
+  double reds[PNW];
+  int rede[PNW];
+  int redi[PNW];
   int nsusp;
   int susp_cell[MAXSUSP];
   int susp_e[MAXSUSP];     // value = susp_m * 2^susp_e (natural scale, or absolute for the cost)
   float susp_m[MAXSUSP];
   int susp_q[MAXSUSP];
-  int xmax[C::NW][XCHUNK];
-  float xsum[C::NW][XCHUNK];
+  int xmax[PNW][XCHUNK];
+  float xsum[PNW][XCHUNK];
 };
 
-// Grid coordinates of register r of the calling lane (accumulator layout).
+// The K x tile buffer: FP32 [D][LDF], after contraction 2, over storage that
+// is dead by then (T in FP32 mode; Tt and K1 in BF16 mode).
 template <int D>
-struct Cell {
-  int i0, j;
-  __device__ Cell() {
-    int tid = threadIdx.x;
-    asm volatile("" : "+v"(tid));   // recompute per use instead of holding every cell's offsets live
-    const int lane = tid & 63, w = tid >> 6;
-    i0 = (w / Cfg<D>::NT) * 32 + 4 * (lane >> 5);
-    j = (w % Cfg<D>::NT) * 32 + (lane & 31);
-  }
-  __device__ int i(int r) const { return i0 + 8 * (r >> 2) + (r & 3); }
-};
-
-// Keeps the scheduler from interleaving the unrolled per-cell iterations (which
-// would hold every cell's temporaries live at once and spill).
-__device__ __forceinline__ void cell_fence() { __builtin_amdgcn_sched_barrier(0); }
+__device__ __forceinline__ float* wbuf(PairSmem<D>& s, bool bf16) {
+  return bf16 ? reinterpret_cast<float*>(s.u.b.Tt) : s.u.f.T;
+}
 
 // Kernel headroom for an input whose residual spans +-mres octaves.
 __device__ __forceinline__ int headroom(int mres) { return max(0, min(HEAD, HEAD + 20 - mres)); }
 
-// R_i = max_k (P_k + ge(i - k)) - H over valid input rows k; rows i >= d get BIG
-// so that their kernel rows are exactly zero.
+// Prefix sum over the workgroup (deterministic): returns the exclusive prefix
+// of v and the total.
+__device__ __forceinline__ int block_scan(int v, int* red, int& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  __syncthreads();
+  if (lane == 63) red[w] = x;
+  __syncthreads();
+  int before = 0, tot = 0;
+  for (int i = 0; i < PNW; ++i) {
+    const int r = red[i];
+    if (i < w) before += r;
+    tot += r;
+  }
+  total = tot;
+  return before + x - v;
+}
+
+// R_i = max_k (P_k + ge(i - k)) - H over valid input rows k (TPR threads per
+// row); rows i >= d get BIG so that their kernel rows are exactly zero.
 template <int D>
 __device__ __forceinline__ void compute_RS(PairSmem<D>& s, const int* P, const int* Q, int d, int H) {
-  for (int r = threadIdx.x; r < 2 * D; r += Cfg<D>::WGS) {
-    const bool rows = r < D;
-    const int i = rows ? r : r - D;
-    const int* X = rows ? P : Q;
-    int best = BIG;
-    if (i < d) {
-      best = NEG;
-#pragma unroll 4
-      for (int k = 0; k < d; ++k) {
-        const int p = X[k];
-        if (p > NEG / 2) best = max(best, p + s.tge[i - k + D - 1]);
-      }
-      best = best <= NEG / 2 ? 0 : best - H;   // empty input: every kernel entry is 0 anyway
+  constexpr int TPR = Cfg<D>::TPR;
+  const int combo = threadIdx.x / TPR, part = threadIdx.x % TPR;
+  const bool rows = combo < D;
+  const int i = rows ? combo : combo - D;
+  const int* X = rows ? P : Q;
+  int best = NEG;
+  if (i < d) {
+    for (int k = part; k < d; k += TPR) {
+      const int p = X[k];
+      if (p > NEG / 2) best = max(best, p + s.tge[i - k + D - 1]);
     }
-    (rows ? s.R : s.S)[i] = best;
+  }
+#pragma unroll
+  for (int o = 1; o < TPR; o <<= 1) best = max(best, __shfl_xor(best, o));
+  if (part == 0) {
+    int r = BIG;
+    if (i < d) r = best <= NEG / 2 ? 0 : best - H;   // empty input: every kernel entry is 0 anyway
+    (rows ? s.R : s.S)[i] = r;
   }
 }
 
@@ -168,11 +198,11 @@ __device__ __forceinline__ float kentry(const PairSmem<D>& s, int i, int k, cons
 }
 
 // BF16 kernels of one application into LDS: K1[i][k] from P and R, K2[j][l]
-// from Q and S; 16 consecutive entries of one row per thread.
+// from Q and S; 16 consecutive entries of one row per thread and step.
 template <int D>
 __device__ __forceinline__ void build_kernels_bf16(PairSmem<D>& s, const int* P, const int* Q) {
   constexpr int LDB = Cfg<D>::LDB;
-  for (int e0 = threadIdx.x * 16; e0 < 2 * D * D; e0 += Cfg<D>::WGS * 16) {
+  for (int e0 = threadIdx.x * 16; e0 < 2 * D * D; e0 += PWGS * 16) {
     const bool first = e0 < D * D;
     const int e = first ? e0 : e0 - D * D;
     const int i = e / D, k0 = e % D;
@@ -190,13 +220,14 @@ __device__ __forceinline__ void build_kernels_bf16(PairSmem<D>& s, const int* P,
   }
 }
 
-// Contraction 1 of Proposition 2 for the calling wave's tile (tk, tj):
+// Contraction 1 of Proposition 2 for the calling wave's tiles (tk, tj):
 //   T[k][j] = sum_l X[k][l] * kt2[j][l]   (kt2 times c1 when WEIGHTED: the m of Prop. 3)
 template <int D, bool BF16, bool WEIGHTED>
 __device__ __forceinline__ void gemm_xk(PairSmem<D>& s, const int* Q) {
   constexpr int NT = Cfg<D>::NT, LDF = Cfg<D>::LDF, LDB = Cfg<D>::LDB;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane & 31, lk = lane >> 5;
-  const int tk = w / NT, tj = w % NT;
+  for (int tile = w; tile < Cfg<D>::NTILES; tile += PNW) {
+  const int tk = tile / NT, tj = tile % NT;
   const int row = tk * 32 + lr, j = tj * 32 + lr;
   floatx16 acc = {};
   if constexpr (BF16) {
@@ -223,91 +254,160 @@ __device__ __forceinline__ void gemm_xk(PairSmem<D>& s, const int* Q) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) s.u.f.T[(tk * 32 + 8 * (r >> 2) + 4 * lk + (r & 3)) * LDF + j] = acc[r];
   }
+  }
 }
 
-// Contraction 2 for the calling wave's tile (ti, tj), result left in registers:
+// Contraction 2 for the calling wave's tiles (ti, tj); after every wave has
+// read T, the tiles go to the K x buffer Wb:
 //   W[i][j] = sum_k kt1[i][k] * T[k][j]   (kt1 times c1 when WEIGHTED)
 template <int D, bool BF16, bool WEIGHTED>
-__device__ __forceinline__ floatx16 gemm_kt(PairSmem<D>& s, const int* P) {
+__device__ __forceinline__ void gemm_kt(PairSmem<D>& s, const int* P, float* Wb) {
   constexpr int NT = Cfg<D>::NT, LDF = Cfg<D>::LDF, LDB = Cfg<D>::LDB;
+  constexpr int TPW = (Cfg<D>::NTILES + PNW - 1) / PNW;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane & 31, lk = lane >> 5;
-  const int ti = w / NT, tj = w % NT;
-  const int i = ti * 32 + lr, j = tj * 32 + lr;
-  floatx16 acc = {};
-  if constexpr (BF16) {
-    const __bf16* ka = s.u.b.K1 + i * LDB + 8 * lk;
-    const __bf16* tb = s.u.b.Tt + j * LDB + 8 * lk;
+  floatx16 acc[TPW];
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) {
+    acc[u] = floatx16{};
+    const int tile = w + u * PNW;
+    if (tile < Cfg<D>::NTILES) {
+      const int ti = tile / NT, tj = tile % NT;
+      const int i = ti * 32 + lr, j = tj * 32 + lr;
+      if constexpr (BF16) {
+        const __bf16* ka = s.u.b.K1 + i * LDB + 8 * lk;
+        const __bf16* tb = s.u.b.Tt + j * LDB + 8 * lk;
 #pragma unroll 2
-    for (int k0 = 0; k0 < D; k0 += 16) {
-      const bf16x8 a = *reinterpret_cast<const bf16x8*>(ka + k0);
-      const bf16x8 b = *reinterpret_cast<const bf16x8*>(tb + k0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-    }
-  } else {
-    const int Ri = s.R[i];
+        for (int k0 = 0; k0 < D; k0 += 16) {
+          const bf16x8 a = *reinterpret_cast<const bf16x8*>(ka + k0);
+          const bf16x8 b = *reinterpret_cast<const bf16x8*>(tb + k0);
+          acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[u], 0, 0, 0);
+        }
+      } else {
+        const int Ri = s.R[i];
 #pragma unroll 4
-    for (int k0 = 0; k0 < D; k0 += 2) {
-      const int k = k0 + lk;
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(kentry<D, WEIGHTED>(s, i, k, P, Ri), s.u.f.T[k * LDF + j], acc,
-                                                 0, 0, 0);
+        for (int k0 = 0; k0 < D; k0 += 2) {
+          const int k = k0 + lk;
+          acc[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(kentry<D, WEIGHTED>(s, i, k, P, Ri), s.u.f.T[k * LDF + j],
+                                                        acc[u], 0, 0, 0);
+        }
+      }
+      mfma_drain();
     }
   }
-  mfma_drain();
-  return acc;
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) {
+    const int tile = w + u * PNW;
+    if (tile < Cfg<D>::NTILES) {
+      const int ti = tile / NT, tj = tile % NT;
+      const int j = tj * 32 + lr;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) Wb[(ti * 32 + 8 * (r >> 2) + 4 * lk + (r & 3)) * LDF + j] = acc[u][r];
+    }
+  }
+  __syncthreads();
 }
 
 // (K x) on the grid for input scales P, Q (residual already in the X buffer of
-// the matching format); returns the calling lane's 16 cells, scaled by
-// 2^-(R_i + S_j).
+// the matching format) into the K x buffer, scaled by 2^-(R_i + S_j).
 template <int D>
-__device__ __forceinline__ floatx16 apply_K(PairSmem<D>& s, const int* P, const int* Q, int d, int H, bool lowp) {
+__device__ __forceinline__ float* apply_K(PairSmem<D>& s, const int* P, const int* Q, int d, int H, bool lowp) {
   compute_RS<D>(s, P, Q, d, H);
   __syncthreads();
-  floatx16 W;
+  float* Wb = wbuf<D>(s, lowp);
   if (lowp) {
     build_kernels_bf16<D>(s, P, Q);
     __syncthreads();
     gemm_xk<D, true, false>(s, Q);
     __syncthreads();
-    W = gemm_kt<D, true, false>(s, P);
+    gemm_kt<D, true, false>(s, P, Wb);
   } else {
     gemm_xk<D, false, false>(s, Q);
     __syncthreads();
-    W = gemm_kt<D, false, false>(s, P);
+    gemm_kt<D, false, false>(s, P, Wb);
+  }
+  return Wb;
+}
+
+// Zero the whole X buffer in format bf16 (then only support cells get set).
+template <int D>
+__device__ __forceinline__ void zero_x(PairSmem<D>& s, bool bf16) {
+  if (bf16) {
+    for (int c = threadIdx.x; c < D * Cfg<D>::LDB / 8; c += PWGS) reinterpret_cast<bf16x8*>(s.u.b.X)[c] = bf16x8{};
+  } else {
+    for (int c = threadIdx.x; c < D * Cfg<D>::LDF; c += PWGS) s.u.f.X[c] = 0.0f;
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void put_x(PairSmem<D>& s, int cell, float v, bool bf16) {
+  const int i = cell / D, j = cell % D;
+  if (bf16) s.u.b.X[i * Cfg<D>::LDB + j] = (__bf16)v;
+  else s.u.f.X[i * Cfg<D>::LDF + j] = v;
+}
+
+// One side's support list in the calling thread's registers.
+template <int SPT>
+struct Support {
+  int cell[SPT];     // i * D + j, or -1
+  float tgt[SPT];    // target marginal at the cell
+  float res[SPT];    // residual of the scaling vector at the cell
+};
+
+// Build the support list of histogram h (d x d, row-major) in deterministic
+// order; returns its total mass and sets too_big when it does not fit.
+template <int D, int SPT>
+__device__ __forceinline__ double build_support(PairSmem<D>& s, const float* __restrict__ h, int d,
+                                                Support<SPT>& sp, bool& too_big) {
+  const int n = d * d;
+  const int per = (n + PWGS - 1) / PWGS;
+  const int c0 = threadIdx.x * per, c1 = min(c0 + per, n);
+  int cnt = 0;
+  double mass = 0.0;
+  for (int c = c0; c < c1; ++c) {
+    const float v = h[c];
+    if (v > 0.0f) {
+      ++cnt;
+      mass += v;
+    }
+  }
+  int total;
+  int off = block_scan(cnt, s.redi, total);
+  mass = block_sum<PNW>(mass, s.red);
+  too_big = total > SPT * PWGS;
+  if (!too_big) {
+    for (int c = c0; c < c1; ++c) {
+      const float v = h[c];
+      if (v > 0.0f) {
+        s.u.st.cell[off] = (c / d) * D + (c % d);
+        s.u.st.val[off] = v;
+        ++off;
+      }
+    }
   }
   __syncthreads();
-  return W;
-}
-
-// Store the calling lane's 16 cells of a residual as the next contraction input.
-template <int D>
-__device__ __forceinline__ void store_x(PairSmem<D>& s, const float (&xt)[CELLS], bool bf16) {
-  const Cell<D> c;
 #pragma unroll
-  for (int r = 0; r < CELLS; ++r) {
-    cell_fence();
-    if (bf16) s.u.b.X[c.i(r) * Cfg<D>::LDB + c.j] = (__bf16)xt[r];
-    else s.u.f.X[c.i(r) * Cfg<D>::LDF + c.j] = xt[r];
+  for (int k = 0; k < SPT; ++k) {
+    const int e = threadIdx.x + PWGS * k;
+    const bool ok = !too_big && e < total;
+    sp.cell[k] = ok ? s.u.st.cell[e] : -1;
+    sp.tgt[k] = ok ? s.u.st.val[e] : 0.0f;
+    sp.res[k] = 0.0f;
   }
+  __syncthreads();
+  return mass;
 }
 
-// Residual of the calling lane's cell r as stored in the X buffer.
-template <int D>
-__device__ __forceinline__ float load_x(const PairSmem<D>& s, const Cell<D>& c, int r, bool bf16) {
-  return bf16 ? (float)s.u.b.X[c.i(r) * Cfg<D>::LDB + c.j] : s.u.f.X[c.i(r) * Cfg<D>::LDF + c.j];
-}
-
-// Exact values for the suspects [base, base + cnt) from the input x (residual
-// in the X buffer in format x_bf16, scales Px, Qx): sum over the support of x of K_(ij),(kl) x_kl (times
-// C_(ij),(kl) when WEIGHTED, Proposition 3) with explicit exponents: pass 1
-// takes each target's largest term exponent, pass 2 the sum of the terms
-// scaled by it.  Writes mantissa and absolute log2 exponent to out_m / out_e.
-template <int D, bool WEIGHTED>
-__device__ __forceinline__ void exact_chunk(PairSmem<D>& s, bool x_bf16, const int* Px, const int* Qx, int base, int cnt,
-                            int* out_e, float* out_m) {
-  constexpr int NW = Cfg<D>::NW;
+// Exact values for the suspects [base, base + cnt) from the input x: sum over
+// the support of x of K_(ij),(kl) x_kl (times C_(ij),(kl) when WEIGHTED,
+// Proposition 3) with explicit exponents: pass 1 takes each target's largest
+// term exponent, pass 2 the sum of the terms scaled by it.  x is its support
+// list, or (dense) 1 on every grid cell.  Writes mantissa and absolute log2
+// exponent to out_m / out_e.
+template <int D, int SPT, bool WEIGHTED>
+__device__ __forceinline__ void exact_chunk(PairSmem<D>& s, const Support<SPT>& xs, bool dense, int d, const int* Px,
+                                            const int* Qx, int base, int cnt, int* out_e, float* out_m) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const Cell<D> cl;
   int ti[XCHUNK], tj[XCHUNK], em[XCHUNK];
 #pragma unroll
   for (int t = 0; t < XCHUNK; ++t) {
@@ -316,15 +416,30 @@ __device__ __forceinline__ void exact_chunk(PairSmem<D>& s, bool x_bf16, const i
     tj[t] = c % D;
     em[t] = QNONE;
   }
+  const int nd = dense ? (d * d + PWGS - 1) / PWGS : SPT;
+  for (int k = 0; k < nd; ++k) {
+    int cell = -1;
+    float x = 0.0f;
+    if (dense) {
+      const int c = tid + PWGS * k;
+      if (c < d * d) {
+        cell = (c / d) * D + (c % d);
+        x = 1.0f;
+      }
+    } else {
 #pragma unroll
-  for (int r = 0; r < CELLS; ++r) {
-    cell_fence();
-    const float x = load_x<D>(s, cl, r, x_bf16);
-    if (x > 0.0f) {
-      const int k = cl.i(r), l = cl.j;
-      const int eb = Px[k] + Qx[l] + ilog2f(x);
+      for (int kk = 0; kk < SPT; ++kk)
+        if (kk == k) {
+          cell = xs.cell[kk];
+          x = xs.res[kk];
+        }
+    }
+    if (cell >= 0 && x > 0.0f) {
+      const int kr = cell / D, l = cell % D;
+      const int eb = Px[kr] + Qx[l] + ilog2f(x);
 #pragma unroll
-      for (int t = 0; t < XCHUNK; ++t) em[t] = max(em[t], eb + s.tge[ti[t] - k + D - 1] + s.tge[tj[t] - l + D - 1]);
+      for (int t = 0; t < XCHUNK; ++t)
+        em[t] = max(em[t], eb + s.tge[ti[t] - kr + D - 1] + s.tge[tj[t] - l + D - 1]);
     }
   }
 #pragma unroll
@@ -338,23 +453,35 @@ __device__ __forceinline__ void exact_chunk(PairSmem<D>& s, bool x_bf16, const i
 #pragma unroll
   for (int t = 0; t < XCHUNK; ++t) {
     int v = s.xmax[0][t];
-#pragma unroll 4
-    for (int w = 1; w < NW; ++w) v = max(v, s.xmax[w][t]);
+    for (int w = 1; w < PNW; ++w) v = max(v, s.xmax[w][t]);
     em[t] = v;
   }
   float acc[XCHUNK];
 #pragma unroll
   for (int t = 0; t < XCHUNK; ++t) acc[t] = 0.0f;
+  for (int k = 0; k < nd; ++k) {
+    int cell = -1;
+    float x = 0.0f;
+    if (dense) {
+      const int c = tid + PWGS * k;
+      if (c < d * d) {
+        cell = (c / d) * D + (c % d);
+        x = 1.0f;
+      }
+    } else {
 #pragma unroll
-  for (int r = 0; r < CELLS; ++r) {
-    cell_fence();
-    const float x = load_x<D>(s, cl, r, x_bf16);
-    if (x > 0.0f) {
-      const int k = cl.i(r), l = cl.j;
-      const int eb = Px[k] + Qx[l];
+      for (int kk = 0; kk < SPT; ++kk)
+        if (kk == k) {
+          cell = xs.cell[kk];
+          x = xs.res[kk];
+        }
+    }
+    if (cell >= 0 && x > 0.0f) {
+      const int kr = cell / D, l = cell % D;
+      const int eb = Px[kr] + Qx[l];
 #pragma unroll
       for (int t = 0; t < XCHUNK; ++t) {
-        const int i1 = ti[t] - k + D - 1, i2 = tj[t] - l + D - 1;
+        const int i1 = ti[t] - kr + D - 1, i2 = tj[t] - l + D - 1;
         float mm = x * s.tgm[i1] * s.tgm[i2];
         if (WEIGHTED) mm *= (s.tc1[i1] + s.tc1[i2]);
         acc[t] += ldx(mm, eb + s.tge[i1] + s.tge[i2] - em[t]);
@@ -372,8 +499,7 @@ __device__ __forceinline__ void exact_chunk(PairSmem<D>& s, bool x_bf16, const i
   if (tid < cnt) {
     float v = 0.0f;
     int e = s.xmax[0][tid];
-#pragma unroll 4
-    for (int w = 0; w < NW; ++w) {
+    for (int w = 0; w < PNW; ++w) {
       v += s.xsum[w][tid];
       e = max(e, s.xmax[w][tid]);
     }
@@ -390,21 +516,22 @@ struct Side {
   int mres;    // residual span (octaves) of its last update
 };
 
-// y = target / (K x), with the lane's cells of K x in W (scaled by 2^-(R+S)),
+// y = target / (K x) on y's support, with K x (scaled by 2^-(R+S)) in Wb
 // except at the suspects.  Refits y's scales (Py, Qy), writes the new residual
-// to yt and, in format out_bf16, to the X buffer, and returns the grid part of
-// <y, k_Delta>.  When `check`, first measures the row-marginal error of the
-// previous y against K x and may stop there, leaving yt, Py, Qy untouched and
-// q holding the suspect markers.
-template <int D>
-__device__ __forceinline__ void y_update(PairSmem<D>& s, const floatx16& W, const float* __restrict__ tgt, int d, const Side& xs,
-                         int H, bool x_bf16, const int* Px, const int* Qx, float (&yt)[CELLS],
-                         int (&q)[CELLS], int* Py, int* Qy, bool out_bf16, bool check, double& err_out,
-                         bool& stop_out, ESum& dot, int& mres_out, int& bad, int& range, double errD, double m,
-                         double tol, double switch_tol, bool& lowp, int t, int max_iter) {
-  constexpr int NW = Cfg<D>::NW, WGS = Cfg<D>::WGS;
+// to ys.res and, in format out_bf16, to the X buffer (clearing the cells of
+// x's support first, or the whole buffer when clear_all), and returns the grid
+// part of <y, k_Delta>.  When `check`, first measures the row-marginal error
+// of the previous y against K x and may stop there, leaving ys, Py, Qy
+// untouched and q holding the suspect markers.
+template <int D, int SPT>
+__device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, Support<SPT>& ys, int (&q)[SPT],
+                                         const Support<SPT>& xsup, bool x_dense, int d, const Side& xs, int H,
+                                         const int* Px, const int* Qx, int* Py, int* Qy, bool out_bf16,
+                                         bool clear_all, bool check, double& err_out, bool& stop_out, ESum& dot,
+                                         int& mres_out, int& bad, int& range, double errD, double m, double tol,
+                                         double switch_tol, bool& lowp, int t, int max_iter) {
+  constexpr int LDF = Cfg<D>::LDF;
   const int tid = threadIdx.x;
-  const Cell<D> cl;
   const float mxf = (float)xs.mx;
   // Trusted level of a normalised value: everything the contractions drop is
   // below 2^(H + mres + 14 - 126) in these units; keep a 2^-40 relative margin.
@@ -413,12 +540,12 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const floatx16& W, cons
   __syncthreads();
   int lbad = 0, lover = 0;
 #pragma unroll
-  for (int r = 0; r < CELLS; ++r) {
-    cell_fence();
-    const int i = cl.i(r), j = cl.j;
-    const float tv = (i < d && j < d) ? tgt[i * d + j] : 0.0f;
-    if (tv > 0.0f) {
-      const float w = W[r];
+  for (int k = 0; k < SPT; ++k) {
+    q[k] = QNONE;
+    const int c = ys.cell[k];
+    if (c >= 0) {
+      const int i = c / D, j = c % D;
+      const float w = Wb[i * LDF + j];
       const int dl = j - i + D - 1;
       const int E = xs.ex + s.tgde[dl] - s.R[i] - s.S[j];
       const float Dm = mxf * s.tgdm[dl];
@@ -428,67 +555,69 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const floatx16& W, cons
       if (le < thr) {
         const int id = atomicAdd(&s.nsusp, 1);
         if (id < MAXSUSP) {
-          s.susp_cell[id] = i * D + j;
-          q[r] = QSUSP + id;
+          s.susp_cell[id] = c;
+          q[k] = QSUSP + id;
         } else {
           lover = 1;
           if (le == QNONE) lbad = 1;
-          q[r] = le == QNONE ? 0 : ilog2f(tv) - le;
+          q[k] = le == QNONE ? 0 : ilog2f(ys.tgt[k]) - le;
         }
       } else {
-        q[r] = ilog2f(tv) - le;
+        q[k] = ilog2f(ys.tgt[k]) - le;
       }
-    } else {
-      q[r] = QNONE;
     }
   }
   __syncthreads();
   const int ns = min(s.nsusp, MAXSUSP);
   if (ns > 0) {
     for (int base = 0; base < ns; base += XCHUNK)
-      exact_chunk<D, false>(s, x_bf16, Px, Qx, base, min(XCHUNK, ns - base), s.susp_e + base, s.susp_m + base);
-    for (int id = tid; id < ns; id += WGS) {
+      exact_chunk<D, SPT, false>(s, xsup, x_dense, d, Px, Qx, base, min(XCHUNK, ns - base), s.susp_e + base,
+                                 s.susp_m + base);
+    for (int id = tid; id < ns; id += PWGS) {
       const int c = s.susp_cell[id], i = c / D, j = c % D;
       const int dl = j - i + D - 1;
       const ESum g{s.susp_e[id] - s.R[i] - s.S[j], (double)s.susp_m[id]};
       const ESum tot = esum_add(g, ESum{xs.ex + s.tgde[dl] - s.R[i] - s.S[j], (double)(mxf * s.tgdm[dl])});
-      if (!(tot.s > 0.0)) {
+      if (tot.s > 0.0) {
+        s.susp_e[id] = tot.e;
+        s.susp_m[id] = (float)tot.s;
+      } else {
         lbad = 1;
         s.susp_e[id] = 0;
         s.susp_m[id] = 1.0f;
-        s.susp_q[id] = 0;
-      } else {
-        const float mt = (float)tot.s;
-        s.susp_e[id] = tot.e;
-        s.susp_m[id] = mt;
-        s.susp_q[id] = ilog2f(tgt[i * d + j]) - (tot.e + ilog2f(mt));
       }
     }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SPT; ++k)
+      if (q[k] >= QSUSP) {
+        const int id = q[k] - QSUSP;
+        s.susp_q[id] = ilog2f(ys.tgt[k]) - (s.susp_e[id] + ilog2f(s.susp_m[id]));
+      }
     __syncthreads();
   }
   if (check) {
     double eg = 0.0;
 #pragma unroll
-    for (int r = 0; r < CELLS; ++r) {
-    cell_fence();
-      if (q[r] != QNONE) {
-        const int i = cl.i(r), j = cl.j;
-        const float tv = tgt[i * d + j];
+    for (int k = 0; k < SPT; ++k) {
+      const int c = ys.cell[k];
+      if (c >= 0) {
+        const int i = c / D, j = c % D;
         const int sh = Py[i] + Qy[j] + s.R[i] + s.S[j];
         double row;
-        if (q[r] >= QSUSP) {
-          const int id = q[r] - QSUSP;
-          row = ldxd((double)yt[r] * (double)s.susp_m[id], s.susp_e[id] + sh);
+        if (q[k] >= QSUSP) {
+          const int id = q[k] - QSUSP;
+          row = ldxd((double)ys.res[k] * (double)s.susp_m[id], s.susp_e[id] + sh);
         } else {
           const int dl = j - i + D - 1;
           const int E = xs.ex + s.tgde[dl] - s.R[i] - s.S[j];
           const float Dm = mxf * s.tgdm[dl];
-          row = ldxd((double)yt[r] * (double)W[r], sh) + ldxd((double)yt[r] * (double)Dm, E + sh);
+          row = ldxd((double)ys.res[k] * (double)Wb[i * LDF + j], sh) + ldxd((double)ys.res[k] * (double)Dm, E + sh);
         }
-        eg += fabs(row - (double)tv);
+        eg += fabs(row - (double)ys.tgt[k]);
       }
     }
-    eg = block_sum<NW>(eg, s.red);
+    eg = block_sum<PNW>(eg, s.red);
     err_out = (eg + errD) / m;
     const bool measured_lowp = lowp;   // never stop on an error measured with BF16 contractions
     if (lowp && err_out <= switch_tol) lowp = false;
@@ -502,50 +631,48 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const floatx16& W, cons
   if (__syncthreads_or(lover)) range = 1;
 
   // Two sweeps of row/column centring of the log2 estimates.
-  for (int r = tid; r < D; r += WGS) {
+  for (int r = tid; r < D; r += PWGS) {
     s.rho[r] = 0;
     s.sig[r] = 0;
   }
   for (int sweep = 0; sweep < 2; ++sweep) {
-    for (int r = tid; r < D; r += WGS) {
+    for (int r = tid; r < D; r += PWGS) {
       s.rmx[r] = INT_MIN;
       s.rmn[r] = INT_MAX;
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < CELLS; ++r) {
-    cell_fence();
-      if (q[r] != QNONE) {
-        const int i = cl.i(r), j = cl.j;
-        const int qv = q[r] >= QSUSP ? s.susp_q[q[r] - QSUSP] : q[r];
+    for (int k = 0; k < SPT; ++k) {
+      if (q[k] != QNONE) {
+        const int c = ys.cell[k], i = c / D, j = c % D;
+        const int qv = q[k] >= QSUSP ? s.susp_q[q[k] - QSUSP] : q[k];
         const int v = qv - s.sig[j];
         atomicMax(&s.rmx[i], v);
         atomicMin(&s.rmn[i], v);
       }
     }
     __syncthreads();
-    for (int r = tid; r < D; r += WGS) {
+    for (int r = tid; r < D; r += PWGS) {
       s.rho[r] = s.rmx[r] != INT_MIN ? ((s.rmx[r] + s.rmn[r]) >> 1) : 0;
       s.cmx[r] = INT_MIN;
       s.cmn[r] = INT_MAX;
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < CELLS; ++r) {
-    cell_fence();
-      if (q[r] != QNONE) {
-        const int i = cl.i(r), j = cl.j;
-        const int qv = q[r] >= QSUSP ? s.susp_q[q[r] - QSUSP] : q[r];
+    for (int k = 0; k < SPT; ++k) {
+      if (q[k] != QNONE) {
+        const int c = ys.cell[k], i = c / D, j = c % D;
+        const int qv = q[k] >= QSUSP ? s.susp_q[q[k] - QSUSP] : q[k];
         const int v = qv - s.rho[i];
         atomicMax(&s.cmx[j], v);
         atomicMin(&s.cmn[j], v);
       }
     }
     __syncthreads();
-    for (int r = tid; r < D; r += WGS) s.sig[r] = s.cmx[r] != INT_MIN ? ((s.cmx[r] + s.cmn[r]) >> 1) : 0;
+    for (int r = tid; r < D; r += PWGS) s.sig[r] = s.cmx[r] != INT_MIN ? ((s.cmx[r] + s.cmn[r]) >> 1) : 0;
     __syncthreads();
   }
-  for (int r = tid; r < D; r += WGS) {
+  for (int r = tid; r < D; r += PWGS) {
     Py[r] = s.rmx[r] != INT_MIN ? s.rho[r] - s.R[r] : NEG;
     Qy[r] = s.cmx[r] != INT_MIN ? s.sig[r] - s.S[r] : NEG;
   }
@@ -554,48 +681,55 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const floatx16& W, cons
   ESum acc{NEG, 0.0};
   int maxres = 0;
 #pragma unroll
-  for (int r = 0; r < CELLS; ++r) {
-    cell_fence();
-    float y = 0.0f;
-    if (q[r] != QNONE) {
-      const int i = cl.i(r), j = cl.j;
-      const float tv = tgt[i * d + j];
+  for (int k = 0; k < SPT; ++k) {
+    const int c = ys.cell[k];
+    if (c >= 0) {
+      const int i = c / D, j = c % D;
       const int dl = j - i + D - 1;
       const int sh = s.rho[i] + s.sig[j];
+      float y;
       int qv;
-      if (q[r] >= QSUSP) {
-        const int id = q[r] - QSUSP;
-        y = tv / ldx(s.susp_m[id], s.susp_e[id] + sh);
+      if (q[k] >= QSUSP) {
+        const int id = q[k] - QSUSP;
+        y = ys.tgt[k] / ldx(s.susp_m[id], s.susp_e[id] + sh);
         qv = s.susp_q[id];
       } else {
         const int E = xs.ex + s.tgde[dl] - s.R[i] - s.S[j];
         const float Dm = mxf * s.tgdm[dl];
-        y = tv / (ldx(W[r], sh) + ldx(Dm, E + sh));
-        qv = q[r];
+        y = ys.tgt[k] / (ldx(Wb[i * LDF + j], sh) + ldx(Dm, E + sh));
+        qv = q[k];
       }
+      ys.res[k] = y;
       maxres = max(maxres, abs(qv - sh));
       acc = esum_add(acc, ESum{Py[i] + Qy[j] + s.tgde[dl], (double)y * (double)s.tgdm[dl]});
     }
-    yt[r] = y;
   }
-  __syncthreads();   // the exact path may still be reading x from the X buffer
-  store_x<D>(s, yt, out_bf16);
-  dot = block_esum<NW>(acc, s.rede, s.reds);
-  mres_out = block_max<NW>(maxres, s.redi) + 1;
+  __syncthreads();   // every read of the K x buffer is done: the X buffer may overlap it
+  if (clear_all) {
+    zero_x<D>(s, out_bf16);
+  } else {
+#pragma unroll
+    for (int k = 0; k < SPT; ++k)
+      if (xsup.cell[k] >= 0) put_x<D>(s, xsup.cell[k], 0.0f, out_bf16);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < SPT; ++k)
+    if (ys.cell[k] >= 0) put_x<D>(s, ys.cell[k], ys.res[k], out_bf16);
+  dot = block_esum<PNW>(acc, s.rede, s.reds);
+  mres_out = block_max<PNW>(maxres, s.redi) + 1;
   if (mres_out > 100) range = 1;
 }
 
-template <int D>
-__global__ __launch_bounds__(Cfg<D>::WGS) void sinkhorn_pair_kernel(PairParams prm) {
-  using C = Cfg<D>;
-  constexpr int NW = C::NW, WGS = C::WGS;
+template <int D, int SPT>
+__global__ __launch_bounds__(PWGS) void sinkhorn_pair_kernel(PairParams prm) {
   __shared__ PairSmem<D> s;
   const int tid = threadIdx.x;
   const long long pair = blockIdx.x;
   const int d = prm.d;
-  const Cell<D> cl;
+  if (prm.only_redo && prm.redo[pair] != prm.only_redo) return;
 
-  for (int x = tid; x < 2 * D; x += WGS) {
+  for (int x = tid; x < 2 * D; x += PWGS) {
     const bool in = x < 2 * D - 1;
     s.tge[x] = in ? prm.ge[x] : NEG;
     s.tgm[x] = in ? prm.gm[x] : 0.0f;
@@ -606,13 +740,15 @@ __global__ __launch_bounds__(Cfg<D>::WGS) void sinkhorn_pair_kernel(PairParams p
   }
   const float* __restrict__ A = prm.hist_a + (size_t)prm.ia[pair] * d * d;
   const float* __restrict__ B = prm.hist_b + (size_t)prm.ib[pair] * d * d;
-  double sa = 0.0, sb = 0.0;
-  for (int c = tid; c < d * d; c += WGS) {
-    sa += A[c];
-    sb += B[c];
+  Support<SPT> ua, vb;   // u on supp(a), v on supp(b)
+  bool big_a, big_b;
+  const double mA = build_support<D, SPT>(s, A, d, ua, big_a);
+  const double mB = build_support<D, SPT>(s, B, d, vb, big_b);
+  if (big_a || big_b) {
+    if (tid == 0) prm.redo[pair] = (unsigned char)(prm.only_redo + 1);
+    return;
   }
-  const double mA = block_sum<NW>(sa, s.red);
-  const double mB = block_sum<NW>(sb, s.red);
+  if (tid == 0) prm.redo[pair] = (unsigned char)prm.only_redo;
   const double aD = mB, bD = mA, m = mA + mB;
   if (m <= 0.0) {
     if (tid == 0) {
@@ -626,51 +762,47 @@ __global__ __launch_bounds__(Cfg<D>::WGS) void sinkhorn_pair_kernel(PairParams p
   }
 
   bool lowp = prm.precision == 1;
-  // u lives in registers (ut) and, between its update and the next contraction,
-  // in the X buffer; v lives in the X buffer only.
-  float ut[CELLS];
-  int q[CELLS];
+  int q[SPT];
   // v = 1 on every grid cell and on the diagonal bin.
-  for (int r = tid; r < D; r += WGS) {
+  for (int r = tid; r < D; r += PWGS) {
     s.Pv[r] = r < d ? 0 : NEG;
     s.Qv[r] = r < d ? 0 : NEG;
     s.Pu[r] = NEG;
     s.Qu[r] = NEG;
   }
   ESum kv{NEG, 0.0};
-  {
-    float v0[CELLS];
+  zero_x<D>(s, lowp);
+  __syncthreads();
+  for (int c = tid; c < d * d; c += PWGS) {
+    const int i = c / d, j = c % d;
+    put_x<D>(s, i * D + j, 1.0f, lowp);
+    kv = esum_add(kv, ESum{s.tgde[j - i + D - 1], (double)s.tgdm[j - i + D - 1]});
+  }
 #pragma unroll
-    for (int r = 0; r < CELLS; ++r) {
-    cell_fence();
-      const int i = cl.i(r), j = cl.j;
-      const bool in = i < d && j < d;
-      v0[r] = in ? 1.0f : 0.0f;
-      ut[r] = 0.0f;
-      q[r] = QNONE;
-      if (in) kv = esum_add(kv, ESum{s.tgde[j - i + D - 1], (double)s.tgdm[j - i + D - 1]});
-    }
-    __syncthreads();
-    store_x<D>(s, v0, lowp);
+  for (int k = 0; k < SPT; ++k) {
+    q[k] = QNONE;
+    vb.res[k] = 1.0f;
   }
   Side su{0, 0.0, 0}, sv{0, 1.0, 0};
-  kv = esum_add(block_esum<NW>(kv, s.rede, s.reds), ESum{0, 1.0});   // (K v)_Delta = <v, k_Delta> + v_Delta
+  kv = esum_add(block_esum<PNW>(kv, s.rede, s.reds), ESum{0, 1.0});   // (K v)_Delta = <v, k_Delta> + v_Delta
   ESum ku{NEG, 0.0};
 
   int t = 0, it_lp = 0, it_hp = 0, bad = 0, range = 0;
-  bool x_lp = lowp;    // format of the residual currently in the X buffer
+  bool x_lp = lowp;      // format of the residual currently in the X buffer
+  bool v_dense = true;   // v is still the all-ones start (dense, not on supp(b))
   double err = INFINITY;
   __syncthreads();
   for (;;) {
     // u-update: u = a / K v, after checking the marginal error of (u, v).
     const bool lp_now = lowp;
     const int Hv = headroom(sv.mres);
-    floatx16 W = apply_K<D>(s, s.Pv, s.Qv, d, Hv, lp_now);
+    const float* Wb = apply_K<D>(s, s.Pv, s.Qv, d, Hv, lp_now);
     bool stop = false;
     ESum dotu;
     const double errD = (t >= 1) ? fabs(ldxd(su.mx * kv.s, su.ex + kv.e) - aD) : 0.0;
-    y_update<D>(s, W, A, d, sv, Hv, x_lp, s.Pv, s.Qv, ut, q, s.Pu, s.Qu, lp_now, t >= 1, err, stop, dotu, su.mres,
-                bad, range, errD, m, prm.tol, prm.switch_tol, lowp, t, prm.max_iter);
+    y_update<D, SPT>(s, Wb, ua, q, vb, v_dense, d, sv, Hv, s.Pv, s.Qv, s.Pu, s.Qu, lp_now,
+                     v_dense || x_lp != lp_now, t >= 1, err, stop, dotu, su.mres, bad, range, errD, m, prm.tol,
+                     prm.switch_tol, lowp, t, prm.max_iter);
     if (stop || bad) break;
     x_lp = lp_now;
     su.ex = -kv.e;
@@ -679,15 +811,17 @@ __global__ __launch_bounds__(Cfg<D>::WGS) void sinkhorn_pair_kernel(PairParams p
     __syncthreads();
     // v-update: v = b / K^T u (K is symmetric).
     const int Hu = headroom(su.mres);
-    W = apply_K<D>(s, s.Pu, s.Qu, d, Hu, lp_now);
+    Wb = apply_K<D>(s, s.Pu, s.Qu, d, Hu, lp_now);
     ESum dotv;
     bool nostop = false;
     double dummy = 0.0;
     {
-      float vnew[CELLS];
-      y_update<D>(s, W, B, d, su, Hu, x_lp, s.Pu, s.Qu, vnew, q, s.Pv, s.Qv, lowp, false, dummy, nostop, dotv,
-                  sv.mres, bad, range, 0.0, m, prm.tol, prm.switch_tol, lowp, t, prm.max_iter);
+      int qv[SPT];
+      y_update<D, SPT>(s, Wb, vb, qv, ua, false, d, su, Hu, s.Pu, s.Qu, s.Pv, s.Qv, lowp, x_lp != lowp, false,
+                       dummy, nostop, dotv, sv.mres, bad, range, 0.0, m, prm.tol, prm.switch_tol, lowp, t,
+                       prm.max_iter);
     }
+    v_dense = false;
     x_lp = lowp;
     sv.ex = -ku.e;
     sv.mx = bD / ku.s;
@@ -702,58 +836,65 @@ __global__ __launch_bounds__(Cfg<D>::WGS) void sinkhorn_pair_kernel(PairParams p
   // Transport cost of Proposition 3 for (u_t, v_t), FP32 contractions and FP64 sums:
   //   sum_ij u_ij (m V k^T + k V m^T)_ij + u_Delta <V, m_Delta> + v_Delta <U, m_Delta>.
   // R, S still hold the scales of the kernels built from (Pv, Qv), and q marks
-  // the cells of supp(a) whose K v needed the exact path: their first term is
-  // recomputed the same way.  v is in the X buffer; as FP32 from here on.
+  // the entries of supp(a) whose K v needed the exact path: their first term
+  // is recomputed the same way.
   __syncthreads();
-  if (x_lp) {
-    float v32[CELLS];
+  zero_x<D>(s, false);
+  __syncthreads();
+  if (v_dense) {
+    for (int c = tid; c < d * d; c += PWGS) put_x<D>(s, (c / d) * D + (c % d), 1.0f, false);
+  } else {
 #pragma unroll
-    for (int r = 0; r < CELLS; ++r) v32[r] = load_x<D>(s, cl, r, true);
-    __syncthreads();
-    store_x<D>(s, v32, false);
+    for (int k = 0; k < SPT; ++k)
+      if (vb.cell[k] >= 0) put_x<D>(s, vb.cell[k], vb.res[k], false);
   }
   __syncthreads();
   double g = 0.0;
+  float* Wf = wbuf<D>(s, false);
   for (int pass = 0; pass < 2; ++pass) {
     if (pass == 0) gemm_xk<D, false, false>(s, s.Qv);
     else gemm_xk<D, false, true>(s, s.Qv);
     __syncthreads();
-    const floatx16 M = pass == 0 ? gemm_kt<D, false, true>(s, s.Pv) : gemm_kt<D, false, false>(s, s.Pv);
-    __syncthreads();
+    if (pass == 0) gemm_kt<D, false, true>(s, s.Pv, Wf);
+    else gemm_kt<D, false, false>(s, s.Pv, Wf);
 #pragma unroll
-    for (int r = 0; r < CELLS; ++r) {
-    cell_fence();
-      if (ut[r] > 0.0f && q[r] < QSUSP) {
-        const int i = cl.i(r), j = cl.j;
-        g += ldxd((double)ut[r] * (double)M[r], s.Pu[i] + s.Qu[j] + s.R[i] + s.S[j]);
+    for (int k = 0; k < SPT; ++k) {
+      const int c = ua.cell[k];
+      if (c >= 0 && ua.res[k] > 0.0f && q[k] < QSUSP) {
+        const int i = c / D, j = c % D;
+        g += ldxd((double)ua.res[k] * (double)Wf[i * Cfg<D>::LDF + j], s.Pu[i] + s.Qu[j] + s.R[i] + s.S[j]);
       }
     }
+    __syncthreads();
   }
   const int ns = bad ? 0 : min(s.nsusp, MAXSUSP);
   if (ns > 0) {
     for (int base = 0; base < ns; base += XCHUNK)
-      exact_chunk<D, true>(s, false, s.Pv, s.Qv, base, min(XCHUNK, ns - base), s.susp_e + base, s.susp_m + base);
+      exact_chunk<D, SPT, true>(s, vb, v_dense, d, s.Pv, s.Qv, base, min(XCHUNK, ns - base), s.susp_e + base,
+                                s.susp_m + base);
 #pragma unroll
-    for (int r = 0; r < CELLS; ++r) {
-    cell_fence();
-      if (q[r] >= QSUSP && ut[r] > 0.0f) {
-        const int i = cl.i(r), j = cl.j;
-        const int id = q[r] - QSUSP;
-        g += ldxd((double)ut[r] * (double)s.susp_m[id], s.susp_e[id] + s.Pu[i] + s.Qu[j]);
+    for (int k = 0; k < SPT; ++k) {
+      if (q[k] >= QSUSP && ua.res[k] > 0.0f) {
+        const int c = ua.cell[k], i = c / D, j = c % D;
+        const int id = q[k] - QSUSP;
+        g += ldxd((double)ua.res[k] * (double)s.susp_m[id], s.susp_e[id] + s.Pu[i] + s.Qu[j]);
       }
     }
   }
 #pragma unroll
-  for (int r = 0; r < CELLS; ++r) {
-    cell_fence();
-    const int i = cl.i(r), j = cl.j;
-    const int dl = j - i + D - 1;
-    const double w = (double)s.tgdm[dl] * (double)s.tcd[dl];
-    const float vr = load_x<D>(s, cl, r, false);
-    if (vr > 0.0f) g += ldxd(su.mx * (double)vr * w, su.ex + s.Pv[i] + s.Qv[j] + s.tgde[dl]);
-    if (ut[r] > 0.0f) g += ldxd(sv.mx * (double)ut[r] * w, sv.ex + s.Pu[i] + s.Qu[j] + s.tgde[dl]);
+  for (int k = 0; k < SPT; ++k) {
+    if (ua.cell[k] >= 0 && ua.res[k] > 0.0f) {
+      const int c = ua.cell[k], i = c / D, j = c % D, dl = j - i + D - 1;
+      g += ldxd(sv.mx * (double)ua.res[k] * (double)s.tgdm[dl] * (double)s.tcd[dl],
+                sv.ex + s.Pu[i] + s.Qu[j] + s.tgde[dl]);
+    }
+    if (!v_dense && vb.cell[k] >= 0 && vb.res[k] > 0.0f) {
+      const int c = vb.cell[k], i = c / D, j = c % D, dl = j - i + D - 1;
+      g += ldxd(su.mx * (double)vb.res[k] * (double)s.tgdm[dl] * (double)s.tcd[dl],
+                su.ex + s.Pv[i] + s.Qv[j] + s.tgde[dl]);
+    }
   }
-  const double cost = block_sum<NW>(g, s.red);
+  const double cost = block_sum<PNW>(g, s.red);
   if (tid == 0) {
     int st = 0;
     if (!(err <= prm.tol)) st |= 1;

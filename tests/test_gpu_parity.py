@@ -167,6 +167,31 @@ def test_edge_cases(pds):
                 assert rel(cost[q], r.cost, m=1.0) <= FP32_RTOL or abs(cost[q] - r.cost) < 1e-9, (d, q)
 
 
+def test_support_size_levels(pds):
+    """Pairs whose supports exceed 512 and 1024 cells (re-run by the wider
+    compact variant and by the dense kernel) match the oracle like small ones."""
+    d, g = 64, 5e-3
+    rng = np.random.default_rng(11)
+
+    def spread(n):
+        b = rng.random(n)
+        t = b + (1.0 - b) * rng.random(n)
+        return np.stack([b, t], 1).astype(np.float32)
+
+    small = pdgen.gen(rng, 40)
+    cases = [(small, pdgen.gen(rng, 60)), (spread(1500), small), (spread(4000), spread(2500)), (small, spread(9000))]
+    with pds.Context(d, g, tol=1e-4, max_iter=3000) as ctx:
+        cost, iters, err, st, hist = run_pairs(pds, ctx, [c[0] for c in cases], [c[1] for c in cases])
+    n = len(cases)
+    supp = [int((hist[q] > 0).sum()) for q in range(2 * n)]
+    assert supp[1] > 512 and supp[n + 2] > 1024 and supp[2] > 1024 and supp[n + 3] > 1024, supp
+    C = dense_C(d)
+    for q in range(n):
+        assert st[q] == 0 and err[q] <= 1e-4, (q, st[q], err[q])
+        r = sinkhorn.sinkhorn(hist[q], hist[n + q], g, max_iter=int(iters[q].sum()), C=C)
+        assert rel(cost[q], r.cost) <= FP32_RTOL, (q, supp[q], supp[n + q], cost[q], r.cost)
+
+
 def test_alone_equals_in_batch(pds):
     """A pair's result does not depend on the batch it runs in (bitwise)."""
     d, g = 64, 2e-3
