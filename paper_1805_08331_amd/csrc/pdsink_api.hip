@@ -28,6 +28,7 @@ struct pdsink_ctx {
   float* gdm;
   float* c1;
   float* cd;
+  int* kb;
 };
 
 namespace {
@@ -52,6 +53,19 @@ void split_pow2(double g, int* e, float* m) {
   if (c < -(double)(1 << 20)) c = -(double)(1 << 20);
   *e = (int)c;
   *m = (float)std::exp2(g - c);
+}
+
+// Table word of a BF16 kernel entry: bf16(m) 2^e (m in (0.5, 1], rounded to
+// nearest even) as (e' << 7) | m7 with bf16(m) 2^e = (1 + m7/128) 2^(e' - 1),
+// so that adding (s << 7) gives the BF16 bit pattern of the entry times 2^(s - 126)
+// whenever that is a normal number.
+int bf16_word(int e, float m) {
+  uint32_t u;
+  std::memcpy(&u, &m, 4);
+  u = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;   // round to nearest even
+  const int field = (int)((u >> 7) & 0xFF);
+  const int m7 = (int)(u & 0x7F);
+  return ((e + field - 126) << 7) | m7;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -136,6 +150,7 @@ int run_pairs(const pdsink_ctx* ctx, int64_t n_pairs, const float* ha, const flo
   pp.gdm = ctx->gdm;
   pp.c1 = ctx->c1;
   pp.cd = ctx->cd;
+  pp.kb = ctx->kb;
   pp.hist_a = ha;
   pp.hist_b = hb;
   pp.ia = ia;
@@ -209,6 +224,7 @@ int pdsink_ctx_create(const pdsink_params* params, int device, pdsink_ctx** out)
   const int n = 2 * D - 1;
   std::vector<int> ge(n), gde(n);
   std::vector<float> gm(n), gdm(n), c1(n), cd(n);
+  std::vector<int> kb(n);
   const double l2e = 1.0 / std::log(2.0);
   for (int x = 0; x < n; ++x) {
     const int delta = std::abs(x - (D - 1));
@@ -219,10 +235,12 @@ int pdsink_ctx_create(const pdsink_params* params, int device, pdsink_ctx** out)
       split_pow2(-cdl / p.gamma * l2e, &gde[x], &gdm[x]);
       c1[x] = (float)c;
       cd[x] = (float)cdl;
+      kb[x] = bf16_word(ge[x], gm[x]);
     } else {
       ge[x] = gde[x] = NEG;
       gm[x] = gdm[x] = 0.0f;
       c1[x] = cd[x] = 0.0f;
+      kb[x] = -(1 << 27);
     }
   }
   pdsink_ctx* ctx = new (std::nothrow) pdsink_ctx;
@@ -232,7 +250,7 @@ int pdsink_ctx_create(const pdsink_params* params, int device, pdsink_ctx** out)
   ctx->device = device;
   ctx->D = D;
   char* base = nullptr;
-  const size_t bytes = (size_t)n * 4 * 6;
+  const size_t bytes = (size_t)n * 4 * 7;
   if (hipMalloc(&base, bytes) != hipSuccess) {
     delete ctx;
     return PDSINK_ENOMEM;
@@ -243,12 +261,14 @@ int pdsink_ctx_create(const pdsink_params* params, int device, pdsink_ctx** out)
   ctx->gdm = (float*)(base + n * 12);
   ctx->c1 = (float*)(base + n * 16);
   ctx->cd = (float*)(base + n * 20);
+  ctx->kb = (int*)(base + n * 24);
   bool ok = hipMemcpy(ctx->ge, ge.data(), n * 4, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(ctx->gm, gm.data(), n * 4, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(ctx->gde, gde.data(), n * 4, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(ctx->gdm, gdm.data(), n * 4, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(ctx->c1, c1.data(), n * 4, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(ctx->cd, cd.data(), n * 4, hipMemcpyHostToDevice) == hipSuccess;
+            hipMemcpy(ctx->cd, cd.data(), n * 4, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(ctx->kb, kb.data(), n * 4, hipMemcpyHostToDevice) == hipSuccess;
   if (!ok) {
     (void)hipFree(base);
     delete ctx;

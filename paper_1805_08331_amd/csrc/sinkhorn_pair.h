@@ -61,6 +61,8 @@ struct PairParams {
   const float* gdm;
   const float* c1;     // (|delta|/d)^p
   const float* cd;     // 2 (|delta|/(2d))^p
+  const int* kb;       // BF16 kernel word: (e << 7) | m7 with 2^g = (1 + m7/128) 2^(e - 1), exactly
+                       // bf16(gm) 2^ge; -(2^27) for |delta| >= d
   // the batch
   const float* hist_a;
   const float* hist_b;
@@ -114,9 +116,13 @@ struct PairSmem {
       float val[D * D];
     } st;
   } u;
-  int tge[2 * D], tgde[2 * D];
+  int tge[2 * D], tgde[2 * D], tkb[2 * D];
   float tgm[2 * D], tgdm[2 * D], tc1[2 * D], tcd[2 * D];
-  int Pu[D], Qu[D], Pv[D], Qv[D], R[D], S[D];
+  alignas(16) int Pu[D];
+  alignas(16) int Qu[D];
+  alignas(16) int Pv[D];
+  alignas(16) int Qv[D];
+  int R[D], S[D];
   int rmx[D], rmn[D], cmx[D], cmn[D], rho[D], sig[D];
   double red[PNW];
   double reds[PNW];
@@ -164,28 +170,52 @@ __device__ __forceinline__ int block_scan(int v, int* red, int& total) {
   return before + x - v;
 }
 
-// R_i = max_k (P_k + ge(i - k)) - H over valid input rows k (TPR threads per
-// row); rows i >= d get BIG so that their kernel rows are exactly zero.
+// R_i = max_k (P_k + ge(i - k)) - H over the input's rows k, and S_j from Q
+// likewise; rows i >= d get BIG so that their kernel rows are exactly zero.
+// Each thread takes 4 consecutive output rows of one side and a slice of k
+// (NPART adjacent lanes share a row block); the 4 table entries it needs
+// slide by one position per k, so each k costs one table read.  Rows of an
+// empty input (every P_k = NEG) get 0: all their kernel entries vanish anyway.
 template <int D>
 __device__ __forceinline__ void compute_RS(PairSmem<D>& s, const int* P, const int* Q, int d, int H) {
-  constexpr int TPR = Cfg<D>::TPR;
-  const int combo = threadIdx.x / TPR, part = threadIdx.x % TPR;
-  const bool rows = combo < D;
-  const int i = rows ? combo : combo - D;
+  constexpr int NRB = 2 * D / 4;         // (side, 4-row block) combinations
+  constexpr int NPART = PWGS / NRB;      // lanes per combination
+  constexpr int KPT = D / NPART;         // k values per lane
+  static_assert(NPART * NRB == PWGS && KPT * NPART == D && NPART <= 64, "compute_RS layout");
+  const int combo = threadIdx.x / NPART, part = threadIdx.x % NPART;
+  const bool rows = combo < NRB / 2;
+  const int i0 = 4 * (rows ? combo : combo - NRB / 2);
   const int* X = rows ? P : Q;
-  int best = NEG;
-  if (i < d) {
-    for (int k = part; k < d; k += TPR) {
-      const int p = X[k];
-      if (p > NEG / 2) best = max(best, p + s.tge[i - k + D - 1]);
+  const int k0 = part * KPT;
+  const int* tw = s.tge + i0 - k0 + D - 1;   // tw[r - (k - k0)] = ge(i0 + r - k)
+  int w0 = tw[0], w1 = tw[1], w2 = tw[2], w3 = tw[3];
+  int b0 = NEG, b1 = NEG, b2 = NEG, b3 = NEG;
+#pragma unroll
+  for (int t = 0; t < KPT; ++t) {
+    const int x = X[k0 + t];
+    b0 = max(b0, x + w0);
+    b1 = max(b1, x + w1);
+    b2 = max(b2, x + w2);
+    b3 = max(b3, x + w3);
+    if (t + 1 < KPT) {
+      w3 = w2;
+      w2 = w1;
+      w1 = w0;
+      w0 = tw[-(t + 1)];
     }
   }
 #pragma unroll
-  for (int o = 1; o < TPR; o <<= 1) best = max(best, __shfl_xor(best, o));
+  for (int o = 1; o < NPART; o <<= 1) {
+    b0 = max(b0, __shfl_xor(b0, o));
+    b1 = max(b1, __shfl_xor(b1, o));
+    b2 = max(b2, __shfl_xor(b2, o));
+    b3 = max(b3, __shfl_xor(b3, o));
+  }
   if (part == 0) {
-    int r = BIG;
-    if (i < d) r = best <= NEG / 2 ? 0 : best - H;   // empty input: every kernel entry is 0 anyway
-    (rows ? s.R : s.S)[i] = r;
+    int* out = (rows ? s.R : s.S) + i0;
+    const int bb[4] = {b0, b1, b2, b3};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[r] = i0 + r < d ? (bb[r] <= NEG / 2 ? 0 : bb[r] - H) : BIG;
   }
 }
 
@@ -198,81 +228,150 @@ __device__ __forceinline__ float kentry(const PairSmem<D>& s, int i, int k, cons
 }
 
 // BF16 kernels of one application into LDS: K1[i][k] from P and R, K2[j][l]
-// from Q and S; 16 consecutive entries of one row per thread and step.
+// from Q and S, 16 consecutive entries of one row per thread and step.  An
+// entry bf16(gm) 2^(P_k + ge - R_i) is assembled directly as a BF16 bit
+// pattern by adding the exponent shift to the table word; results below the
+// smallest normal BF16 (2^-126, at least 2^-166 below the row maximum) are 0.
 template <int D>
 __device__ __forceinline__ void build_kernels_bf16(PairSmem<D>& s, const int* P, const int* Q) {
   constexpr int LDB = Cfg<D>::LDB;
-  for (int e0 = threadIdx.x * 16; e0 < 2 * D * D; e0 += PWGS * 16) {
-    const bool first = e0 < D * D;
-    const int e = first ? e0 : e0 - D * D;
-    const int i = e / D, k0 = e % D;
-    const int* X = first ? P : Q;
-    const int Ri = (first ? s.R : s.S)[i];
-    __bf16* dst = (first ? s.u.b.K1 : s.u.b.K2) + i * LDB + k0;
-    bf16x8 v0, v1;
+  constexpr int NCH = D / 16;             // 16-entry chunks per row
+  // item = ((side * NCH + chunk) * D + row): adjacent lanes take adjacent rows
+  // of one chunk, so their table reads hit adjacent LDS banks.
+  for (int item = threadIdx.x; item < 2 * NCH * D; item += PWGS) {
+    const int i = item % D, sc = item / D;
+    const bool first = sc < NCH;
+    const int k0 = 16 * (first ? sc : sc - NCH);
+    const int* X = (first ? P : Q) + k0;
+    const int base = 126 - (first ? s.R : s.S)[i];
+    const int* tw = s.tkb + i - k0 + D - 1;    // tw[-t] = word of delta = i - (k0 + t)
+    const int4 xa = *reinterpret_cast<const int4*>(X), xb = *reinterpret_cast<const int4*>(X + 4);
+    const int4 xc = *reinterpret_cast<const int4*>(X + 8), xd = *reinterpret_cast<const int4*>(X + 12);
+    const int xs[16] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w, xc.x, xc.y, xc.z, xc.w, xd.x, xd.y, xd.z, xd.w};
+    unsigned int pk[8];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      v0[t] = (__bf16)kentry<D, false>(s, i, k0 + t, X, Ri);
-      v1[t] = (__bf16)kentry<D, false>(s, i, k0 + 8 + t, X, Ri);
+    for (int t = 0; t < 16; t += 2) {
+      const int s0 = min(max(xs[t] + base, -(1 << 20)), 1 << 20);
+      const int s1 = min(max(xs[t + 1] + base, -(1 << 20)), 1 << 20);
+      int v0 = tw[-t] + (s0 << 7);
+      int v1 = tw[-t - 1] + (s1 << 7);
+      v0 = v0 >= 128 ? v0 : 0;
+      v1 = v1 >= 128 ? v1 : 0;
+      pk[t >> 1] = (unsigned)v0 | ((unsigned)v1 << 16);
     }
-    *reinterpret_cast<bf16x8*>(dst) = v0;
-    *reinterpret_cast<bf16x8*>(dst + 8) = v1;
+    uint4* dst = reinterpret_cast<uint4*>((first ? s.u.b.K1 : s.u.b.K2) + i * LDB + k0);
+    dst[0] = uint4{pk[0], pk[1], pk[2], pk[3]};
+    dst[1] = uint4{pk[4], pk[5], pk[6], pk[7]};
   }
+}
+
+// Tile schedules.  Histogram supports of persistence diagrams lie on or above
+// the diagonal (birth <= death), so when every support of the pair does
+// ("tri"), u and v vanish below it: contraction 1 skips the l-blocks below a
+// row block of X (X[k][l] = 0 for l < k), and contraction 2 computes only the
+// output tiles on or above the diagonal, the only cells the update, the error
+// and the cost read.  Tiles are spread so that the matrix cores of the four
+// SIMDs (waves w and w + 4 share one) get equal work.
+
+// Contraction 1 tile `u` (0 or 1) of wave w: returns false when there is none.
+template <int D>
+__device__ __forceinline__ bool xk_tile(int w, int u, int& tk, int& tj) {
+  constexpr int NT = Cfg<D>::NT;
+  if constexpr (NT == 4) {
+    // column tj = w mod 4 per SIMD; row blocks {0, 3} and {1, 2} per wave:
+    // 5 of the 10 trimmed l-blocks of that column each.
+    tj = w & 3;
+    tk = (w < 4) ? (u == 0 ? 0 : 3) : (u == 0 ? 1 : 2);
+    return true;
+  } else {
+    const int tile = w + u * PNW;
+    tk = tile / NT;
+    tj = tile % NT;
+    return tile < NT * NT;
+  }
+}
+
+// Contraction 2 tile `u` of wave w among the upper tiles (tri) or all tiles.
+template <int D>
+__device__ __forceinline__ bool kt_tile(int w, int u, bool tri, int& ti, int& tj) {
+  constexpr int NT = Cfg<D>::NT;
+  int tile = w + u * PNW;
+  if (!tri) {
+    ti = tile / NT;
+    tj = tile % NT;
+    return tile < NT * NT;
+  }
+  if (tile >= NT * (NT + 1) / 2) return false;
+  ti = 0;
+  while (tile >= NT - ti) {
+    tile -= NT - ti;
+    ++ti;
+  }
+  tj = ti + tile;
+  return true;
 }
 
 // Contraction 1 of Proposition 2 for the calling wave's tiles (tk, tj):
 //   T[k][j] = sum_l X[k][l] * kt2[j][l]   (kt2 times c1 when WEIGHTED: the m of Prop. 3)
+// With `trim`, X is zero below the diagonal and l starts at the tile's first row.
 template <int D, bool BF16, bool WEIGHTED>
-__device__ __forceinline__ void gemm_xk(PairSmem<D>& s, const int* Q) {
-  constexpr int NT = Cfg<D>::NT, LDF = Cfg<D>::LDF, LDB = Cfg<D>::LDB;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane & 31, lk = lane >> 5;
-  for (int tile = w; tile < Cfg<D>::NTILES; tile += PNW) {
-  const int tk = tile / NT, tj = tile % NT;
-  const int row = tk * 32 + lr, j = tj * 32 + lr;
-  floatx16 acc = {};
-  if constexpr (BF16) {
-    const __bf16* xa = s.u.b.X + row * LDB + 8 * lk;
-    const __bf16* kb = s.u.b.K2 + j * LDB + 8 * lk;
+__device__ __forceinline__ void gemm_xk(PairSmem<D>& s, const int* Q, bool trim) {
+  constexpr int LDF = Cfg<D>::LDF, LDB = Cfg<D>::LDB;
+  const int lane = threadIdx.x & 63, lr = lane & 31, lk = lane >> 5;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave index, held in a scalar register
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    int tk, tj;
+    if (!xk_tile<D>(w, u, tk, tj)) break;
+    const int row = tk * 32 + lr, j = tj * 32 + lr;
+    const int lbeg = trim ? tk * 32 : 0;
+    floatx16 acc = {};
+    if constexpr (BF16) {
+      const __bf16* xa = s.u.b.X + row * LDB + 8 * lk;
+      const __bf16* kb = s.u.b.K2 + j * LDB + 8 * lk;
 #pragma unroll 2
-    for (int l0 = 0; l0 < D; l0 += 16) {
-      const bf16x8 a = *reinterpret_cast<const bf16x8*>(xa + l0);
-      const bf16x8 b = *reinterpret_cast<const bf16x8*>(kb + l0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-    }
-    mfma_drain();
+      for (int l0 = lbeg; l0 < D; l0 += 16) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(xa + l0);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(kb + l0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+      }
+      mfma_drain();
 #pragma unroll
-    for (int r = 0; r < 16; ++r) s.u.b.Tt[j * LDB + tk * 32 + 8 * (r >> 2) + 4 * lk + (r & 3)] = (__bf16)acc[r];
-  } else {
-    const int Sj = s.S[j];
+      for (int r = 0; r < 16; ++r) s.u.b.Tt[j * LDB + tk * 32 + 8 * (r >> 2) + 4 * lk + (r & 3)] = (__bf16)acc[r];
+    } else {
+      const int Sj = s.S[j];
 #pragma unroll 4
-    for (int l0 = 0; l0 < D; l0 += 2) {
-      const int l = l0 + lk;
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(s.u.f.X[row * LDF + l], kentry<D, WEIGHTED>(s, j, l, Q, Sj), acc,
-                                                 0, 0, 0);
-    }
-    mfma_drain();
+      for (int l0 = lbeg; l0 < D; l0 += 2) {
+        const int l = l0 + lk;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(s.u.f.X[row * LDF + l], kentry<D, WEIGHTED>(s, j, l, Q, Sj), acc,
+                                                   0, 0, 0);
+      }
+      mfma_drain();
 #pragma unroll
-    for (int r = 0; r < 16; ++r) s.u.f.T[(tk * 32 + 8 * (r >> 2) + 4 * lk + (r & 3)) * LDF + j] = acc[r];
-  }
+      for (int r = 0; r < 16; ++r) s.u.f.T[(tk * 32 + 8 * (r >> 2) + 4 * lk + (r & 3)) * LDF + j] = acc[r];
+    }
   }
 }
 
 // Contraction 2 for the calling wave's tiles (ti, tj); after every wave has
 // read T, the tiles go to the K x buffer Wb:
 //   W[i][j] = sum_k kt1[i][k] * T[k][j]   (kt1 times c1 when WEIGHTED)
+// With `tri`, only tiles on or above the diagonal are computed.
 template <int D, bool BF16, bool WEIGHTED>
-__device__ __forceinline__ void gemm_kt(PairSmem<D>& s, const int* P, float* Wb) {
-  constexpr int NT = Cfg<D>::NT, LDF = Cfg<D>::LDF, LDB = Cfg<D>::LDB;
+__device__ __forceinline__ void gemm_kt(PairSmem<D>& s, const int* P, float* Wb, bool tri) {
+  constexpr int LDF = Cfg<D>::LDF, LDB = Cfg<D>::LDB;
   constexpr int TPW = (Cfg<D>::NTILES + PNW - 1) / PNW;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane & 31, lk = lane >> 5;
+  const int lane = threadIdx.x & 63, lr = lane & 31, lk = lane >> 5;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave index, held in a scalar register
   floatx16 acc[TPW];
+  bool has[TPW];
+  int tis[TPW], tjs[TPW];
 #pragma unroll
   for (int u = 0; u < TPW; ++u) {
     acc[u] = floatx16{};
-    const int tile = w + u * PNW;
-    if (tile < Cfg<D>::NTILES) {
-      const int ti = tile / NT, tj = tile % NT;
-      const int i = ti * 32 + lr, j = tj * 32 + lr;
+    has[u] = kt_tile<D>(w, u, tri, tis[u], tjs[u]);
+    if (has[u]) {
+      const int i = tis[u] * 32 + lr, j = tjs[u] * 32 + lr;
       if constexpr (BF16) {
         const __bf16* ka = s.u.b.K1 + i * LDB + 8 * lk;
         const __bf16* tb = s.u.b.Tt + j * LDB + 8 * lk;
@@ -297,34 +396,34 @@ __device__ __forceinline__ void gemm_kt(PairSmem<D>& s, const int* P, float* Wb)
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < TPW; ++u) {
-    const int tile = w + u * PNW;
-    if (tile < Cfg<D>::NTILES) {
-      const int ti = tile / NT, tj = tile % NT;
-      const int j = tj * 32 + lr;
+    if (has[u]) {
+      const int j = tjs[u] * 32 + lr;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) Wb[(ti * 32 + 8 * (r >> 2) + 4 * lk + (r & 3)) * LDF + j] = acc[u][r];
+      for (int r = 0; r < 16; ++r) Wb[(tis[u] * 32 + 8 * (r >> 2) + 4 * lk + (r & 3)) * LDF + j] = acc[u][r];
     }
   }
   __syncthreads();
 }
 
 // (K x) on the grid for input scales P, Q (residual already in the X buffer of
-// the matching format) into the K x buffer, scaled by 2^-(R_i + S_j).
+// the matching format) into the K x buffer, scaled by 2^-(R_i + S_j).  `trim`:
+// x vanishes below the diagonal; `tri`: only cells on or above it are read.
 template <int D>
-__device__ __forceinline__ float* apply_K(PairSmem<D>& s, const int* P, const int* Q, int d, int H, bool lowp) {
+__device__ __forceinline__ float* apply_K(PairSmem<D>& s, const int* P, const int* Q, int d, int H, bool lowp,
+                                          bool trim, bool tri) {
   compute_RS<D>(s, P, Q, d, H);
   __syncthreads();
   float* Wb = wbuf<D>(s, lowp);
   if (lowp) {
     build_kernels_bf16<D>(s, P, Q);
     __syncthreads();
-    gemm_xk<D, true, false>(s, Q);
+    gemm_xk<D, true, false>(s, Q, trim);
     __syncthreads();
-    gemm_kt<D, true, false>(s, P, Wb);
+    gemm_kt<D, true, false>(s, P, Wb, tri);
   } else {
-    gemm_xk<D, false, false>(s, Q);
+    gemm_xk<D, false, false>(s, Q, trim);
     __syncthreads();
-    gemm_kt<D, false, false>(s, P, Wb);
+    gemm_kt<D, false, false>(s, P, Wb, tri);
   }
   return Wb;
 }
@@ -355,22 +454,25 @@ struct Support {
 };
 
 // Build the support list of histogram h (d x d, row-major) in deterministic
-// order; returns its total mass and sets too_big when it does not fit.
+// order; returns its total mass, sets too_big when it does not fit and lower
+// when some mass lies below the diagonal (cell column < row).
 template <int D, int SPT>
 __device__ __forceinline__ double build_support(PairSmem<D>& s, const float* __restrict__ h, int d,
-                                                Support<SPT>& sp, bool& too_big) {
+                                                Support<SPT>& sp, bool& too_big, bool& lower) {
   const int n = d * d;
   const int per = (n + PWGS - 1) / PWGS;
   const int c0 = threadIdx.x * per, c1 = min(c0 + per, n);
-  int cnt = 0;
+  int cnt = 0, low = 0;
   double mass = 0.0;
   for (int c = c0; c < c1; ++c) {
     const float v = h[c];
     if (v > 0.0f) {
       ++cnt;
       mass += v;
+      low |= (c % d) < (c / d);
     }
   }
+  lower = __syncthreads_or(low);
   int total;
   int off = block_scan(cnt, s.redi, total);
   mass = block_sum<PNW>(mass, s.red);
@@ -732,6 +834,7 @@ __global__ __launch_bounds__(PWGS) void sinkhorn_pair_kernel(PairParams prm) {
   for (int x = tid; x < 2 * D; x += PWGS) {
     const bool in = x < 2 * D - 1;
     s.tge[x] = in ? prm.ge[x] : NEG;
+    s.tkb[x] = in ? prm.kb[x] : -(1 << 27);
     s.tgm[x] = in ? prm.gm[x] : 0.0f;
     s.tgde[x] = in ? prm.gde[x] : NEG;
     s.tgdm[x] = in ? prm.gdm[x] : 0.0f;
@@ -741,9 +844,10 @@ __global__ __launch_bounds__(PWGS) void sinkhorn_pair_kernel(PairParams prm) {
   const float* __restrict__ A = prm.hist_a + (size_t)prm.ia[pair] * d * d;
   const float* __restrict__ B = prm.hist_b + (size_t)prm.ib[pair] * d * d;
   Support<SPT> ua, vb;   // u on supp(a), v on supp(b)
-  bool big_a, big_b;
-  const double mA = build_support<D, SPT>(s, A, d, ua, big_a);
-  const double mB = build_support<D, SPT>(s, B, d, vb, big_b);
+  bool big_a, big_b, low_a, low_b;
+  const double mA = build_support<D, SPT>(s, A, d, ua, big_a, low_a);
+  const double mB = build_support<D, SPT>(s, B, d, vb, big_b, low_b);
+  const bool tri = !low_a && !low_b;   // u and v vanish below the diagonal
   if (big_a || big_b) {
     if (tid == 0) prm.redo[pair] = (unsigned char)(prm.only_redo + 1);
     return;
@@ -796,7 +900,7 @@ __global__ __launch_bounds__(PWGS) void sinkhorn_pair_kernel(PairParams prm) {
     // u-update: u = a / K v, after checking the marginal error of (u, v).
     const bool lp_now = lowp;
     const int Hv = headroom(sv.mres);
-    const float* Wb = apply_K<D>(s, s.Pv, s.Qv, d, Hv, lp_now);
+    const float* Wb = apply_K<D>(s, s.Pv, s.Qv, d, Hv, lp_now, tri && !v_dense, tri);
     bool stop = false;
     ESum dotu;
     const double errD = (t >= 1) ? fabs(ldxd(su.mx * kv.s, su.ex + kv.e) - aD) : 0.0;
@@ -811,7 +915,7 @@ __global__ __launch_bounds__(PWGS) void sinkhorn_pair_kernel(PairParams prm) {
     __syncthreads();
     // v-update: v = b / K^T u (K is symmetric).
     const int Hu = headroom(su.mres);
-    Wb = apply_K<D>(s, s.Pu, s.Qu, d, Hu, lp_now);
+    Wb = apply_K<D>(s, s.Pu, s.Qu, d, Hu, lp_now, tri, tri);
     ESum dotv;
     bool nostop = false;
     double dummy = 0.0;
@@ -852,11 +956,11 @@ __global__ __launch_bounds__(PWGS) void sinkhorn_pair_kernel(PairParams prm) {
   double g = 0.0;
   float* Wf = wbuf<D>(s, false);
   for (int pass = 0; pass < 2; ++pass) {
-    if (pass == 0) gemm_xk<D, false, false>(s, s.Qv);
-    else gemm_xk<D, false, true>(s, s.Qv);
+    if (pass == 0) gemm_xk<D, false, false>(s, s.Qv, tri && !v_dense);
+    else gemm_xk<D, false, true>(s, s.Qv, tri && !v_dense);
     __syncthreads();
-    if (pass == 0) gemm_kt<D, false, true>(s, s.Pv, Wf);
-    else gemm_kt<D, false, false>(s, s.Pv, Wf);
+    if (pass == 0) gemm_kt<D, false, true>(s, s.Pv, Wf, tri);
+    else gemm_kt<D, false, false>(s, s.Pv, Wf, tri);
 #pragma unroll
     for (int k = 0; k < SPT; ++k) {
       const int c = ua.cell[k];
