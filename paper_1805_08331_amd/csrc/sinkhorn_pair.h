@@ -123,7 +123,9 @@ struct PairSmem {
   alignas(16) int Pv[D];
   alignas(16) int Qv[D];
   int R[D], S[D];
-  int rmx[D], rmn[D], cmx[D], cmn[D], rho[D], sig[D];
+  // refit extrema: [sweep][row max, row min, column max, column min][D]
+  int fit[2][4][D];
+  int sflag;               // bit 0: a suspect's exact value vanished
   double red[PNW];
   double reds[PNW];
   int rede[PNW];
@@ -132,7 +134,6 @@ struct PairSmem {
   int susp_cell[MAXSUSP];
   int susp_e[MAXSUSP];     // value = susp_m * 2^susp_e (natural scale, or absolute for the cost)
   float susp_m[MAXSUSP];
-  int susp_q[MAXSUSP];
   int xmax[PNW][XCHUNK];
   float xsum[PNW][XCHUNK];
 };
@@ -411,6 +412,7 @@ __device__ __forceinline__ void gemm_kt(PairSmem<D>& s, const int* P, float* Wb,
 template <int D>
 __device__ __forceinline__ float* apply_K(PairSmem<D>& s, const int* P, const int* Q, int d, int H, bool lowp,
                                           bool trim, bool tri) {
+  prep_update<D>(s);
   compute_RS<D>(s, P, Q, d, H);
   __syncthreads();
   float* Wb = wbuf<D>(s, lowp);
@@ -618,32 +620,65 @@ struct Side {
   int mres;    // residual span (octaves) of its last update
 };
 
+// Reset the per-half-step state of y_update (suspect count, flags, refit
+// extrema); called before the K application that feeds it.
+template <int D>
+__device__ __forceinline__ void prep_update(PairSmem<D>& s) {
+  for (int r = threadIdx.x; r < D; r += PWGS) {
+#pragma unroll
+    for (int sw = 0; sw < 2; ++sw) {
+      s.fit[sw][0][r] = INT_MIN;
+      s.fit[sw][1][r] = INT_MAX;
+      s.fit[sw][2][r] = INT_MIN;
+      s.fit[sw][3][r] = INT_MAX;
+    }
+  }
+  if (threadIdx.x == 0) {
+    s.nsusp = 0;
+    s.sflag = 0;
+  }
+}
+
+__device__ __forceinline__ int midrange(const int* mx, const int* mn, int r) { return (mx[r] + mn[r]) >> 1; }
+
 // y = target / (K x) on y's support, with K x (scaled by 2^-(R+S)) in Wb
 // except at the suspects.  Refits y's scales (Py, Qy), writes the new residual
-// to ys.res and, in format out_bf16, to the X buffer (clearing the cells of
-// x's support first, or the whole buffer when clear_all), and returns the grid
+// to ys.res and, in format out_bf16, to the X buffer (after clearing the cells
+// of x's support, or the whole buffer when clear_all), and returns the grid
 // part of <y, k_Delta>.  When `check`, first measures the row-marginal error
 // of the previous y against K x and may stop there, leaving ys, Py, Qy
-// untouched and q holding the suspect markers.
+// untouched and q holding the suspect markers.  `wb_bf16`: Wb lies in the
+// BF16 buffers, which an FP32 X buffer overlaps.
+//
+// The refit is two sweeps of row/column centring of the per-cell log2
+// estimates: each of the four passes folds its extrema into LDS with atomics,
+// and the centre of the previous pass is read on the fly, so a half step
+// needs five workgroup barriers when no cell is suspect.
 template <int D, int SPT>
-__device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, Support<SPT>& ys, int (&q)[SPT],
-                                         const Support<SPT>& xsup, bool x_dense, int d, const Side& xs, int H,
-                                         const int* Px, const int* Qx, int* Py, int* Qy, bool out_bf16,
-                                         bool clear_all, bool check, double& err_out, bool& stop_out, ESum& dot,
-                                         int& mres_out, int& bad, int& range, double errD, double m, double tol,
-                                         double switch_tol, bool& lowp, int t, int max_iter) {
+__device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, bool wb_bf16, Support<SPT>& ys,
+                                         int (&q)[SPT], const Support<SPT>& xsup, bool x_dense, int d,
+                                         const Side& xs, int H, const int* Px, const int* Qx, int* Py, int* Qy,
+                                         bool out_bf16, bool clear_all, bool check, double& err_out, bool& stop_out,
+                                         ESum& dot, int& mres_out, int& bad, int& range, double errD, double m,
+                                         double tol, double switch_tol, bool& lowp, int t, int max_iter) {
   constexpr int LDF = Cfg<D>::LDF;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const float mxf = (float)xs.mx;
   // Trusted level of a normalised value: everything the contractions drop is
   // below 2^(H + mres + 14 - 126) in these units; keep a 2^-40 relative margin.
   const int thr = H + max(xs.mres, 20) + 14 - 126 + 40;
-  if (tid == 0) s.nsusp = 0;
-  __syncthreads();
+  // The X buffer can be cleared now (x was consumed by contraction 1) unless
+  // an FP32 X overlaps the BF16 K x buffer still being read.
+  const bool late_x = !out_bf16 && wb_bf16;
+  int qe[SPT];   // log2 estimate of the new y at the entry (QNONE: no entry)
+
+  // Pass A: suspects, row extrema of sweep 0, error terms, X clearing.
   int lbad = 0, lover = 0;
+  double eg = 0.0;
 #pragma unroll
   for (int k = 0; k < SPT; ++k) {
     q[k] = QNONE;
+    qe[k] = QNONE;
     const int c = ys.cell[k];
     if (c >= 0) {
       const int i = c / D, j = c % D;
@@ -654,11 +689,13 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, Suppor
       const int lw = w > 0.0f ? ilog2f(w) : QNONE;
       const int ld = Dm > 0.0f ? E + ilog2f(Dm) : QNONE;
       const int le = max(lw, ld);
+      bool sus = false;
       if (le < thr) {
         const int id = atomicAdd(&s.nsusp, 1);
         if (id < MAXSUSP) {
           s.susp_cell[id] = c;
           q[k] = QSUSP + id;
+          sus = true;
         } else {
           lover = 1;
           if (le == QNONE) lbad = 1;
@@ -667,10 +704,47 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, Suppor
       } else {
         q[k] = ilog2f(ys.tgt[k]) - le;
       }
+      if (!sus) {
+        qe[k] = q[k];
+        atomicMax(&s.fit[0][0][i], q[k]);
+        atomicMin(&s.fit[0][1][i], q[k]);
+        if (check) {
+          const int sh = Py[i] + Qy[j] + s.R[i] + s.S[j];
+          const double row =
+              ldxd((double)ys.res[k] * (double)w, sh) + ldxd((double)ys.res[k] * (double)Dm, E + sh);
+          eg += fabs(row - (double)ys.tgt[k]);
+        }
+      }
+    }
+  }
+  if (!late_x) {
+    if (clear_all) {
+      zero_x<D>(s, out_bf16);
+    } else {
+#pragma unroll
+      for (int k = 0; k < SPT; ++k)
+        if (xsup.cell[k] >= 0) put_x<D>(s, xsup.cell[k], 0.0f, out_bf16);
+    }
+  }
+  {
+    const double egw = wave_sum(eg);
+    const unsigned long long bb = __ballot(lbad), bo = __ballot(lover);
+    if (lane == 0) {
+      s.red[wave] = egw;
+      s.redi[wave] = (bb ? 1 : 0) | (bo ? 2 : 0);
     }
   }
   __syncthreads();
   const int ns = min(s.nsusp, MAXSUSP);
+  double egs = 0.0;
+  int flags = 0;
+#pragma unroll
+  for (int w = 0; w < PNW; ++w) {
+    egs += s.red[w];
+    flags |= s.redi[w];
+  }
+
+  // Suspects: exact values, then their row extrema and error terms.
   if (ns > 0) {
     for (int base = 0; base < ns; base += XCHUNK)
       exact_chunk<D, SPT, false>(s, xsup, x_dense, d, Px, Qx, base, min(XCHUNK, ns - base), s.susp_e + base,
@@ -684,102 +758,87 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, Suppor
         s.susp_e[id] = tot.e;
         s.susp_m[id] = (float)tot.s;
       } else {
-        lbad = 1;
+        atomicOr(&s.sflag, 1);
         s.susp_e[id] = 0;
         s.susp_m[id] = 1.0f;
       }
     }
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < SPT; ++k)
-      if (q[k] >= QSUSP) {
-        const int id = q[k] - QSUSP;
-        s.susp_q[id] = ilog2f(ys.tgt[k]) - (s.susp_e[id] + ilog2f(s.susp_m[id]));
-      }
-    __syncthreads();
-  }
-  if (check) {
-    double eg = 0.0;
+    double eg2 = 0.0;
 #pragma unroll
     for (int k = 0; k < SPT; ++k) {
-      const int c = ys.cell[k];
-      if (c >= 0) {
-        const int i = c / D, j = c % D;
-        const int sh = Py[i] + Qy[j] + s.R[i] + s.S[j];
-        double row;
-        if (q[k] >= QSUSP) {
-          const int id = q[k] - QSUSP;
-          row = ldxd((double)ys.res[k] * (double)s.susp_m[id], s.susp_e[id] + sh);
-        } else {
-          const int dl = j - i + D - 1;
-          const int E = xs.ex + s.tgde[dl] - s.R[i] - s.S[j];
-          const float Dm = mxf * s.tgdm[dl];
-          row = ldxd((double)ys.res[k] * (double)Wb[i * LDF + j], sh) + ldxd((double)ys.res[k] * (double)Dm, E + sh);
+      if (q[k] >= QSUSP) {
+        const int id = q[k] - QSUSP;
+        const int c = ys.cell[k], i = c / D, j = c % D;
+        qe[k] = ilog2f(ys.tgt[k]) - (s.susp_e[id] + ilog2f(s.susp_m[id]));
+        atomicMax(&s.fit[0][0][i], qe[k]);
+        atomicMin(&s.fit[0][1][i], qe[k]);
+        if (check) {
+          const int sh = Py[i] + Qy[j] + s.R[i] + s.S[j];
+          const double row = ldxd((double)ys.res[k] * (double)s.susp_m[id], s.susp_e[id] + sh);
+          eg2 += fabs(row - (double)ys.tgt[k]);
         }
-        eg += fabs(row - (double)ys.tgt[k]);
       }
     }
-    eg = block_sum<PNW>(eg, s.red);
-    err_out = (eg + errD) / m;
+    eg2 = wave_sum(eg2);
+    if (lane == 0) s.reds[wave] = eg2;
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < PNW; ++w) egs += s.reds[w];
+    flags |= s.sflag;
+  }
+
+  if (check) {
+    err_out = (egs + errD) / m;
     const bool measured_lowp = lowp;   // never stop on an error measured with BF16 contractions
     if (lowp && err_out <= switch_tol) lowp = false;
     if ((!measured_lowp && err_out <= tol) || t >= max_iter) {
       stop_out = true;
-      if (__syncthreads_or(lbad)) bad = 1;
+      if (flags & 1) bad = 1;
       return;
     }
   }
-  if (__syncthreads_or(lbad)) bad = 1;
-  if (__syncthreads_or(lover)) range = 1;
+  if (flags & 1) bad = 1;
+  if (flags & 2) range = 1;
 
-  // Two sweeps of row/column centring of the log2 estimates.
-  for (int r = tid; r < D; r += PWGS) {
-    s.rho[r] = 0;
-    s.sig[r] = 0;
-  }
-  for (int sweep = 0; sweep < 2; ++sweep) {
-    for (int r = tid; r < D; r += PWGS) {
-      s.rmx[r] = INT_MIN;
-      s.rmn[r] = INT_MAX;
-    }
-    __syncthreads();
+  // Column extrema of sweep 0 (against the row centres of sweep 0), then the
+  // rows and columns of sweep 1.
 #pragma unroll
-    for (int k = 0; k < SPT; ++k) {
-      if (q[k] != QNONE) {
-        const int c = ys.cell[k], i = c / D, j = c % D;
-        const int qv = q[k] >= QSUSP ? s.susp_q[q[k] - QSUSP] : q[k];
-        const int v = qv - s.sig[j];
-        atomicMax(&s.rmx[i], v);
-        atomicMin(&s.rmn[i], v);
-      }
+  for (int k = 0; k < SPT; ++k) {
+    if (qe[k] != QNONE) {
+      const int c = ys.cell[k], i = c / D, j = c % D;
+      const int v = qe[k] - midrange(s.fit[0][0], s.fit[0][1], i);
+      atomicMax(&s.fit[0][2][j], v);
+      atomicMin(&s.fit[0][3][j], v);
     }
-    __syncthreads();
-    for (int r = tid; r < D; r += PWGS) {
-      s.rho[r] = s.rmx[r] != INT_MIN ? ((s.rmx[r] + s.rmn[r]) >> 1) : 0;
-      s.cmx[r] = INT_MIN;
-      s.cmn[r] = INT_MAX;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < SPT; ++k) {
-      if (q[k] != QNONE) {
-        const int c = ys.cell[k], i = c / D, j = c % D;
-        const int qv = q[k] >= QSUSP ? s.susp_q[q[k] - QSUSP] : q[k];
-        const int v = qv - s.rho[i];
-        atomicMax(&s.cmx[j], v);
-        atomicMin(&s.cmn[j], v);
-      }
-    }
-    __syncthreads();
-    for (int r = tid; r < D; r += PWGS) s.sig[r] = s.cmx[r] != INT_MIN ? ((s.cmx[r] + s.cmn[r]) >> 1) : 0;
-    __syncthreads();
   }
-  for (int r = tid; r < D; r += PWGS) {
-    Py[r] = s.rmx[r] != INT_MIN ? s.rho[r] - s.R[r] : NEG;
-    Qy[r] = s.cmx[r] != INT_MIN ? s.sig[r] - s.S[r] : NEG;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < SPT; ++k) {
+    if (qe[k] != QNONE) {
+      const int c = ys.cell[k], i = c / D, j = c % D;
+      const int v = qe[k] - midrange(s.fit[0][2], s.fit[0][3], j);
+      atomicMax(&s.fit[1][0][i], v);
+      atomicMin(&s.fit[1][1][i], v);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < SPT; ++k) {
+    if (qe[k] != QNONE) {
+      const int c = ys.cell[k], i = c / D, j = c % D;
+      const int v = qe[k] - midrange(s.fit[1][0], s.fit[1][1], i);
+      atomicMax(&s.fit[1][2][j], v);
+      atomicMin(&s.fit[1][3][j], v);
+    }
   }
   __syncthreads();
 
+  // New scales: natural (-R, -S) plus the centres (rho, sigma) of sweep 1.
+  for (int r = tid; r < D; r += PWGS) {
+    Py[r] = s.fit[1][0][r] != INT_MIN ? midrange(s.fit[1][0], s.fit[1][1], r) - s.R[r] : NEG;
+    Qy[r] = s.fit[1][2][r] != INT_MIN ? midrange(s.fit[1][2], s.fit[1][3], r) - s.S[r] : NEG;
+  }
   ESum acc{NEG, 0.0};
   int maxres = 0;
 #pragma unroll
@@ -788,39 +847,50 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, Suppor
     if (c >= 0) {
       const int i = c / D, j = c % D;
       const int dl = j - i + D - 1;
-      const int sh = s.rho[i] + s.sig[j];
+      const int rho = midrange(s.fit[1][0], s.fit[1][1], i), sig = midrange(s.fit[1][2], s.fit[1][3], j);
+      const int sh = rho + sig;
       float y;
-      int qv;
       if (q[k] >= QSUSP) {
         const int id = q[k] - QSUSP;
         y = ys.tgt[k] / ldx(s.susp_m[id], s.susp_e[id] + sh);
-        qv = s.susp_q[id];
       } else {
         const int E = xs.ex + s.tgde[dl] - s.R[i] - s.S[j];
         const float Dm = mxf * s.tgdm[dl];
         y = ys.tgt[k] / (ldx(Wb[i * LDF + j], sh) + ldx(Dm, E + sh));
-        qv = q[k];
       }
       ys.res[k] = y;
-      maxres = max(maxres, abs(qv - sh));
-      acc = esum_add(acc, ESum{Py[i] + Qy[j] + s.tgde[dl], (double)y * (double)s.tgdm[dl]});
+      if (!late_x) put_x<D>(s, c, y, out_bf16);
+      maxres = max(maxres, abs(qe[k] - sh));
+      acc = esum_add(acc, ESum{rho - s.R[i] + sig - s.S[j] + s.tgde[dl], (double)y * (double)s.tgdm[dl]});
     }
   }
-  __syncthreads();   // every read of the K x buffer is done: the X buffer may overlap it
-  if (clear_all) {
-    zero_x<D>(s, out_bf16);
-  } else {
-#pragma unroll
-    for (int k = 0; k < SPT; ++k)
-      if (xsup.cell[k] >= 0) put_x<D>(s, xsup.cell[k], 0.0f, out_bf16);
+  {
+    const ESum aw = wave_esum(acc);
+    const int mw = wave_max(maxres);
+    if (lane == 0) {
+      s.rede[wave] = aw.e;
+      s.reds[wave] = aw.s;
+      s.redi[wave] = mw;
+    }
   }
   __syncthreads();
+  ESum tot{s.rede[0], s.reds[0]};
+  int mr = s.redi[0];
 #pragma unroll
-  for (int k = 0; k < SPT; ++k)
-    if (ys.cell[k] >= 0) put_x<D>(s, ys.cell[k], ys.res[k], out_bf16);
-  dot = block_esum<PNW>(acc, s.rede, s.reds);
-  mres_out = block_max<PNW>(maxres, s.redi) + 1;
+  for (int w = 1; w < PNW; ++w) {
+    tot = esum_add(tot, ESum{s.rede[w], s.reds[w]});
+    mr = max(mr, s.redi[w]);
+  }
+  dot = tot;
+  mres_out = mr + 1;
   if (mres_out > 100) range = 1;
+  if (late_x) {   // switch of the X format: every read of the K x buffer is done now
+    zero_x<D>(s, out_bf16);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SPT; ++k)
+      if (ys.cell[k] >= 0) put_x<D>(s, ys.cell[k], ys.res[k], out_bf16);
+  }
 }
 
 template <int D, int SPT>
@@ -904,7 +974,7 @@ __global__ __launch_bounds__(PWGS) void sinkhorn_pair_kernel(PairParams prm) {
     bool stop = false;
     ESum dotu;
     const double errD = (t >= 1) ? fabs(ldxd(su.mx * kv.s, su.ex + kv.e) - aD) : 0.0;
-    y_update<D, SPT>(s, Wb, ua, q, vb, v_dense, d, sv, Hv, s.Pv, s.Qv, s.Pu, s.Qu, lp_now,
+    y_update<D, SPT>(s, Wb, lp_now, ua, q, vb, v_dense, d, sv, Hv, s.Pv, s.Qv, s.Pu, s.Qu, lp_now,
                      v_dense || x_lp != lp_now, t >= 1, err, stop, dotu, su.mres, bad, range, errD, m, prm.tol,
                      prm.switch_tol, lowp, t, prm.max_iter);
     if (stop || bad) break;
@@ -921,7 +991,7 @@ __global__ __launch_bounds__(PWGS) void sinkhorn_pair_kernel(PairParams prm) {
     double dummy = 0.0;
     {
       int qv[SPT];
-      y_update<D, SPT>(s, Wb, vb, qv, ua, false, d, su, Hu, s.Pu, s.Qu, s.Pv, s.Qv, lowp, x_lp != lowp, false,
+      y_update<D, SPT>(s, Wb, lp_now, vb, qv, ua, false, d, su, Hu, s.Pu, s.Qu, s.Pv, s.Qv, lowp, x_lp != lowp, false,
                        dummy, nostop, dotv, sv.mres, bad, range, 0.0, m, prm.tol, prm.switch_tol, lowp, t,
                        prm.max_iter);
     }
