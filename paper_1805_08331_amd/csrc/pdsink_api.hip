@@ -11,7 +11,7 @@
 
 #include "../../include/pdsink.h"
 #include "pdsink_device.h"
-#include "sinkhorn_dense.h"
+#include "sinkhorn_pair.h"
 #include "sinkhorn_pair.h"
 
 using namespace pdsink;
@@ -29,6 +29,7 @@ struct pdsink_ctx {
   float* c1;
   float* cd;
   int* kb;
+  int n_cu;           // compute units of the device: workgroups of the global-list variant
 };
 
 namespace {
@@ -106,38 +107,45 @@ __global__ __launch_bounds__(WG) void discretize_kernel(const float* __restrict_
   if (threadIdx.x == 0) mass[n] = kept;
 }
 
-template <int D, int SPT>
-int launch_pairs(PairParams pp, int level, hipStream_t st) {
-  pp.only_redo = level;
-  hipLaunchKernelGGL((sinkhorn_pair_kernel<D, SPT>), dim3((unsigned)pp.n_pairs), dim3(PWGS), 0, st, pp);
-  return last_error();
-}
+// Optional per-pair buffers of a distance launch.
+struct PairExtras {
+  char* lists = nullptr;      // global support lists, list_bytes(D) per workgroup slot
+  int n_slots = 0;            // workgroup slots (grid of the global-list variant)
+  char* state = nullptr;      // WarmState per pair
+  int state_in = 0;
+  double* gout = nullptr;     // [n_pairs][d * d] gradient terms
+};
 
-template <int D>
-int launch_dense(PairParams pp, int level, hipStream_t st) {
-  pp.only_redo = level;
-  hipLaunchKernelGGL((dense::sinkhorn_pair_kernel<D>), dim3((unsigned)pp.n_pairs), dim3(dense::Cfg<D>::WGS), 0, st,
-                     pp);
-  return last_error();
+size_t list_bytes(int D) { return align256((size_t)40 * D * D); }   // 2 sides x 5 arrays x D^2 x 4 bytes
+size_t warm_bytes(int D) {
+  switch (D) {
+    case 32: return sizeof(WarmState<32>);
+    case 64: return sizeof(WarmState<64>);
+    default: return sizeof(WarmState<128>);
+  }
 }
+int64_t slots_for(const pdsink_ctx* ctx, int64_t n_pairs) { return n_pairs < ctx->n_cu ? n_pairs : ctx->n_cu; }
 
-// Level 0 runs every pair in the compact kernel with one support entry per
-// thread (supports up to 512 cells per side); pairs that do not fit flag
-// themselves and run again at level 1 with two entries per thread (1024
-// cells), then at level 2 in the dense kernel.  All launches go to the same
-// stream, with no host synchronisation; a level with no flagged pair exits at
-// once.
+// Level 0 runs every pair with one support entry per thread and register
+// lists (supports up to 512 cells per side); pairs that do not fit flag
+// themselves and run at level 1 with their lists in the workspace, one
+// workgroup per compute unit striding over the batch.  Both launches go to
+// the same stream, with no host synchronisation; when no pair is flagged the
+// second launch only reads the flags.
 template <int D>
-int launch_levels(PairParams pp, hipStream_t st) {
-  int rc = launch_pairs<D, 1>(pp, 0, st);
-  if (!rc) rc = launch_pairs<D, 2>(pp, 1, st);
-  if (!rc) rc = launch_dense<D>(pp, 2, st);
-  return rc;
+int launch_levels(PairParams pp, int n_slots, hipStream_t st) {
+  pp.only_redo = 0;
+  hipLaunchKernelGGL((sinkhorn_pair_kernel<D, 1>), dim3((unsigned)pp.n_pairs), dim3(PWGS), 0, st, pp);
+  int rc = last_error();
+  if (rc) return rc;
+  pp.only_redo = 1;
+  hipLaunchKernelGGL((sinkhorn_pair_kernel<D, 0>), dim3((unsigned)n_slots), dim3(PWGS), 0, st, pp);
+  return last_error();
 }
 
 int run_pairs(const pdsink_ctx* ctx, int64_t n_pairs, const float* ha, const float* hb, const int32_t* ia,
               const int32_t* ib, double* cost, int32_t* iters, float* err, int32_t* status, unsigned char* redo,
-              hipStream_t st) {
+              const PairExtras& ex, hipStream_t st) {
   PairParams pp;
   pp.d = ctx->prm.d;
   pp.tol = ctx->prm.tol;
@@ -161,10 +169,15 @@ int run_pairs(const pdsink_ctx* ctx, int64_t n_pairs, const float* ha, const flo
   pp.err = err;
   pp.status = status;
   pp.redo = redo;
+  pp.lists = ex.lists;
+  pp.list_stride = list_bytes(ctx->D);
+  pp.state = ex.state;
+  pp.state_in = ex.state_in;
+  pp.gout = ex.gout;
   switch (ctx->D) {
-    case 32: return launch_levels<32>(pp, st);
-    case 64: return launch_levels<64>(pp, st);
-    default: return launch_levels<128>(pp, st);
+    case 32: return launch_levels<32>(pp, ex.n_slots, st);
+    case 64: return launch_levels<64>(pp, ex.n_slots, st);
+    default: return launch_levels<128>(pp, ex.n_slots, st);
   }
 }
 
@@ -196,6 +209,48 @@ __global__ void kmeans_argmin_kernel(int64_t n_diag, int k, const double* __rest
 
 
 }  // namespace
+
+// Barycenter pairs: q = (z, hist[q]).
+__global__ void bary_pairs_kernel(int64_t n, int32_t* ia, int32_t* ib) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q < n) {
+    ia[q] = 0;
+    ib[q] = (int32_t)q;
+  }
+}
+
+// Mass of each histogram (FP64, fixed order within the workgroup).
+__global__ __launch_bounds__(WG) void hist_mass_kernel(const float* __restrict__ hist, int d, double* mass) {
+  __shared__ double red[NWAVE];
+  const int64_t n = blockIdx.x;
+  double m = 0.0;
+  for (int c = threadIdx.x; c < d * d; c += WG) m += hist[n * d * d + c];
+  m = block_sum(m, red);
+  if (threadIdx.x == 0) mass[n] = m;
+}
+
+// Uniform measure on the cells j >= i with the mean of the N masses.
+__global__ void bary_uniform_kernel(const double* mass, int64_t n, int d, float* z) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= d * d) return;
+  double m = 0.0;
+  for (int64_t q = 0; q < n; ++q) m += mass[q];
+  m /= (double)n;
+  const int i = c / d, j = c % d;
+  z[c] = j >= i ? (float)(m / (0.5 * d * (d + 1))) : 0.0f;
+}
+
+// Multiplicative step of Algorithm 2 on the support of z, gradient summed
+// over the diagrams in a fixed order.
+__global__ void bary_step_kernel(const double* __restrict__ gout, int64_t n, int d, double scale, float* z) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= d * d) return;
+  const float zc = z[c];
+  if (!(zc > 0.0f)) return;
+  double gsum = 0.0;
+  for (int64_t q = 0; q < n; ++q) gsum += gout[q * d * d + c];
+  z[c] = (float)((double)zc * exp(-scale * gsum));
+}
 
 extern "C" {
 
@@ -249,6 +304,11 @@ int pdsink_ctx_create(const pdsink_params* params, int device, pdsink_ctx** out)
   ctx->prm = p;
   ctx->device = device;
   ctx->D = D;
+  {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || ncu < 1) ncu = 1;
+    ctx->n_cu = ncu;
+  }
   char* base = nullptr;
   const size_t bytes = (size_t)n * 4 * 7;
   if (hipMalloc(&base, bytes) != hipSuccess) {
@@ -294,12 +354,18 @@ int pdsink_ctx_params(const pdsink_ctx* ctx, pdsink_params* out) {
 int pdsink_workspace_bytes(const pdsink_ctx* ctx, int op, int64_t n_items, size_t* bytes) {
   if (!ctx || !bytes || n_items < 0) return PDSINK_EINVAL;
   switch (op) {
-    case PDSINK_OP_DIST: *bytes = align256(n_items); return PDSINK_OK;
-    case PDSINK_OP_KMEANS:   // ia, ib, cost, iters, err, status, redo per pair
-      *bytes = align256(n_items * 4) * 2 + align256(n_items * 8) + align256(n_items * 8) + align256(n_items * 4) * 2 +
-               align256(n_items);
+    case PDSINK_OP_DIST:   // routing flag per pair, support lists per slot
+      *bytes = align256(n_items) + slots_for(ctx, n_items) * list_bytes(ctx->D);
       return PDSINK_OK;
-    case PDSINK_OP_BARYCENTER: *bytes = 256; return PDSINK_OK;
+    case PDSINK_OP_KMEANS:   // ia, ib, cost, iters, err, status, redo per pair, lists per slot
+      *bytes = align256(n_items * 4) * 2 + align256(n_items * 8) + align256(n_items * 8) + align256(n_items * 4) * 2 +
+               align256(n_items) + slots_for(ctx, n_items) * list_bytes(ctx->D);
+      return PDSINK_OK;
+    case PDSINK_OP_BARYCENTER:   // the KMEANS arrays for n pairs, warm states, gradient terms
+      *bytes = align256(n_items * 4) * 2 + align256(n_items * 8) + align256(n_items * 8) + align256(n_items * 4) * 2 +
+               align256(n_items) + slots_for(ctx, n_items) * list_bytes(ctx->D) +
+               align256(n_items * warm_bytes(ctx->D)) + align256(n_items * 8 * (size_t)ctx->prm.d * ctx->prm.d);
+      return PDSINK_OK;
     default: return PDSINK_EINVAL;
   }
 }
@@ -329,7 +395,10 @@ int sinkhorn_dist_batch(pdsink_ctx* ctx, int64_t n_pairs, const float* hist_a, c
   if (!ws || ws_bytes < need) return PDSINK_ENOMEM;
   DeviceGuard g(ctx->device);
   if (!g.ok) return PDSINK_EDEVICE;
-  return run_pairs(ctx, n_pairs, hist_a, hist_b, ia, ib, cost, iters, err, status, (unsigned char*)ws,
+  PairExtras ex;
+  ex.lists = (char*)ws + align256(n_pairs);
+  ex.n_slots = (int)slots_for(ctx, n_pairs);
+  return run_pairs(ctx, n_pairs, hist_a, hist_b, ia, ib, cost, iters, err, status, (unsigned char*)ws, ex,
                    (hipStream_t)stream);
 }
 
@@ -359,11 +428,15 @@ int kmeans_assign(pdsink_ctx* ctx, int64_t n_diag, const float* hist, int32_t k,
   int32_t* st = (int32_t*)w;
   w += align256(np * 4);
   unsigned char* redo = (unsigned char*)w;
+  w += align256(np);
+  PairExtras ex;
+  ex.lists = w;
+  ex.n_slots = (int)slots_for(ctx, np);
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(kmeans_pairs_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, n_diag, k, ia, ib);
   int rc = last_error();
   if (rc) return rc;
-  rc = run_pairs(ctx, np, hist, centroids, ia, ib, cost, iters, err, st, redo, s);
+  rc = run_pairs(ctx, np, hist, centroids, ia, ib, cost, iters, err, st, redo, ex, s);
   if (rc) return rc;
   hipLaunchKernelGGL(kmeans_argmin_kernel, dim3((unsigned)((n_diag + 255) / 256)), dim3(256), 0, s, n_diag, k, cost,
                      assign, dist, st, status);
@@ -373,9 +446,78 @@ int kmeans_assign(pdsink_ctx* ctx, int64_t n_diag, const float* hist, int32_t k,
 int pd_barycenter(pdsink_ctx* ctx, int64_t n_diag, const float* hist, double lambda, int32_t max_outer,
                   double energy_rtol, int32_t init_uniform, float* z, double* energy, int32_t* outer, void* ws,
                   size_t ws_bytes, void* stream) {
-  (void)ctx; (void)n_diag; (void)hist; (void)lambda; (void)max_outer; (void)energy_rtol; (void)init_uniform;
-  (void)z; (void)energy; (void)outer; (void)ws; (void)ws_bytes; (void)stream;
-  return PDSINK_EINVAL;   // implemented in the barycenter source
+  if (!ctx || n_diag < 1 || n_diag > INT_MAX || !hist || !z || !energy || !outer || max_outer < 1 ||
+      !(lambda >= 0.0) || !std::isfinite(lambda) || !(energy_rtol >= 0.0))
+    return PDSINK_EINVAL;
+  const int64_t N = n_diag;
+  size_t need = 0;
+  pdsink_workspace_bytes(ctx, PDSINK_OP_BARYCENTER, N, &need);
+  if (!ws || ws_bytes < need) return PDSINK_ENOMEM;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return PDSINK_EDEVICE;
+  const int d = ctx->prm.d;
+  char* w = (char*)ws;
+  int32_t* ia = (int32_t*)w;
+  w += align256(N * 4);
+  int32_t* ib = (int32_t*)w;
+  w += align256(N * 4);
+  double* cost = (double*)w;
+  w += align256(N * 8);
+  int32_t* iters = (int32_t*)w;
+  w += align256(N * 8);
+  float* err = (float*)w;
+  w += align256(N * 4);
+  int32_t* st = (int32_t*)w;
+  w += align256(N * 4);
+  unsigned char* redo = (unsigned char*)w;
+  w += align256(N);
+  PairExtras ex;
+  ex.lists = w;
+  ex.n_slots = (int)slots_for(ctx, N);
+  w += ex.n_slots * list_bytes(ctx->D);
+  ex.state = w;
+  w += align256(N * warm_bytes(ctx->D));
+  ex.gout = (double*)w;
+  hipStream_t s = (hipStream_t)stream;
+
+  hipLaunchKernelGGL(bary_pairs_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, ia, ib);
+  int rc = last_error();
+  if (rc) return rc;
+  if (init_uniform) {
+    // uniform on the cells j >= i, total mass = mean diagram mass (reusing cost[] for the masses)
+    hipLaunchKernelGGL(hist_mass_kernel, dim3((unsigned)N), dim3(WG), 0, s, hist, d, cost);
+    hipLaunchKernelGGL(bary_uniform_kernel, dim3((unsigned)((d * d + 255) / 256)), dim3(256), 0, s, cost, N, d, z);
+    if ((rc = last_error())) return rc;
+  }
+  std::vector<double> hc(N);
+  std::vector<int32_t> hs(N);
+  double E = 0.0, E_prev = 0.0;
+  int t = 0;
+  for (t = 0; t < max_outer; ++t) {
+    ex.state_in = t > 0;
+    rc = run_pairs(ctx, N, z, hist, ia, ib, cost, iters, err, st, redo, ex, s);
+    if (rc) return rc;
+    if (hipMemcpyAsync(hc.data(), cost, N * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(hs.data(), st, N * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return PDSINK_EDEVICE;
+    double sum = 0.0;
+    for (int64_t q = 0; q < N; ++q) {
+      if (hs[q] & PDSINK_ST_NONFINITE) return PDSINK_ERANGE;
+      sum += hc[q];
+    }
+    E = sum / (double)N;
+    if (t > 0 && std::fabs(E / E_prev - 1.0) < energy_rtol) break;
+    if (t == max_outer - 1) break;
+    // z <- z exp(-lambda grad), grad = (gamma / N) sum_i (log u_i + log v_i,Delta)  (Proposition 5)
+    hipLaunchKernelGGL(bary_step_kernel, dim3((unsigned)((d * d + 255) / 256)), dim3(256), 0, s, ex.gout, N, d,
+                       lambda * ctx->prm.gamma / (double)N, z);
+    if ((rc = last_error())) return rc;
+    E_prev = E;
+  }
+  *energy = E;
+  *outer = t + 1;
+  return PDSINK_OK;
 }
 
 }  // extern "C"

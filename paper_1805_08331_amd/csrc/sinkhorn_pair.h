@@ -79,6 +79,16 @@ struct PairParams {
   // does not fit the variant; else it sets redo[q] = L.
   unsigned char* redo;
   int only_redo;
+  // support lists of the global-list variant: list_stride bytes per workgroup
+  char* lists;
+  size_t list_stride;
+  // optional warm start of v (WarmState per pair): read when state_in, and
+  // written with the final v
+  char* state;
+  int state_in;
+  // optional gradient terms of Proposition 5, [n_pairs][d * d]: log u + log
+  // v_Delta on the cells of supp(a)
+  double* gout;
 };
 
 constexpr int PWGS = 512;      // threads per pair workgroup
@@ -447,12 +457,67 @@ __device__ __forceinline__ void put_x(PairSmem<D>& s, int cell, float v, bool bf
   else s.u.f.X[i * Cfg<D>::LDF + j] = v;
 }
 
-// One side's support list in the calling thread's registers.
+// One side's support list (u on supp(a) or v on supp(b)): per entry the cell
+// i * D + j, the target marginal, the scaling residual, the marker q (log2
+// estimate, or QSUSP + suspect index) and the refit estimate qe.  Entry e
+// belongs to thread e mod PWGS, slot e / PWGS; only its owner touches it.
+// SPT > 0: SPT slots per thread in registers.  SPT = 0: the entries live in a
+// per-workgroup slice of the workspace (L2-resident), for supports of any size.
 template <int SPT>
-struct Support {
-  int cell[SPT];     // i * D + j, or -1
-  float tgt[SPT];    // target marginal at the cell
-  float res[SPT];    // residual of the scaling vector at the cell
+struct SupList {
+  int cell_[SPT];
+  float tgt_[SPT];
+  float res_[SPT];
+  int q_[SPT];
+  int qe_[SPT];
+  __device__ __forceinline__ static constexpr int nk() { return SPT; }
+  __device__ __forceinline__ int cell(int k) const { return cell_[k]; }
+  __device__ __forceinline__ float tgt(int k) const { return tgt_[k]; }
+  __device__ __forceinline__ float res(int k) const { return res_[k]; }
+  __device__ __forceinline__ int q(int k) const { return q_[k]; }
+  __device__ __forceinline__ int qe(int k) const { return qe_[k]; }
+  __device__ __forceinline__ void set_res(int k, float v) { res_[k] = v; }
+  __device__ __forceinline__ void set_q(int k, int v) { q_[k] = v; }
+  __device__ __forceinline__ void set_qe(int k, int v) { qe_[k] = v; }
+  __device__ __forceinline__ void set_entry(int k, int c, float t) {
+    cell_[k] = c;
+    tgt_[k] = t;
+    res_[k] = 0.0f;
+  }
+  __device__ __forceinline__ static constexpr int capacity() { return SPT * PWGS; }
+};
+
+template <>
+struct SupList<0> {
+  int* cell_;
+  float* tgt_;
+  float* res_;
+  int* q_;
+  int* qe_;
+  int n;
+  int cap;
+  __device__ __forceinline__ int nk() const { return (n + PWGS - 1) / PWGS; }
+  __device__ __forceinline__ int ix(int k) const { return (int)threadIdx.x + PWGS * k; }
+  __device__ __forceinline__ int cell(int k) const { return ix(k) < n ? cell_[ix(k)] : -1; }
+  __device__ __forceinline__ float tgt(int k) const { return ix(k) < n ? tgt_[ix(k)] : 0.0f; }
+  __device__ __forceinline__ float res(int k) const { return ix(k) < n ? res_[ix(k)] : 0.0f; }
+  __device__ __forceinline__ int q(int k) const { return ix(k) < n ? q_[ix(k)] : QNONE; }
+  __device__ __forceinline__ int qe(int k) const { return ix(k) < n ? qe_[ix(k)] : QNONE; }
+  __device__ __forceinline__ void set_res(int k, float v) {
+    if (ix(k) < n) res_[ix(k)] = v;
+  }
+  __device__ __forceinline__ void set_q(int k, int v) {
+    if (ix(k) < n) q_[ix(k)] = v;
+  }
+  __device__ __forceinline__ void set_qe(int k, int v) {
+    if (ix(k) < n) qe_[ix(k)] = v;
+  }
+  __device__ __forceinline__ void set_entry(int k, int c, float t) {
+    cell_[ix(k)] = c;
+    tgt_[ix(k)] = t;
+    res_[ix(k)] = 0.0f;
+  }
+  __device__ __forceinline__ int capacity() const { return cap; }
 };
 
 // Build the support list of histogram h (d x d, row-major) in deterministic
@@ -460,7 +525,7 @@ struct Support {
 // when some mass lies below the diagonal (cell column < row).
 template <int D, int SPT>
 __device__ __forceinline__ double build_support(PairSmem<D>& s, const float* __restrict__ h, int d,
-                                                Support<SPT>& sp, bool& too_big, bool& lower) {
+                                                SupList<SPT>& sp, bool& too_big, bool& lower) {
   const int n = d * d;
   const int per = (n + PWGS - 1) / PWGS;
   const int c0 = threadIdx.x * per, c1 = min(c0 + per, n);
@@ -478,7 +543,7 @@ __device__ __forceinline__ double build_support(PairSmem<D>& s, const float* __r
   int total;
   int off = block_scan(cnt, s.redi, total);
   mass = block_sum<PNW>(mass, s.red);
-  too_big = total > SPT * PWGS;
+  too_big = total > sp.capacity();
   if (!too_big) {
     for (int c = c0; c < c1; ++c) {
       const float v = h[c];
@@ -490,13 +555,17 @@ __device__ __forceinline__ double build_support(PairSmem<D>& s, const float* __r
     }
   }
   __syncthreads();
+  if constexpr (SPT == 0) sp.n = too_big ? 0 : total;
+  const int nk = sp.nk();
 #pragma unroll
-  for (int k = 0; k < SPT; ++k) {
+  for (int k = 0; k < nk; ++k) {
     const int e = threadIdx.x + PWGS * k;
     const bool ok = !too_big && e < total;
-    sp.cell[k] = ok ? s.u.st.cell[e] : -1;
-    sp.tgt[k] = ok ? s.u.st.val[e] : 0.0f;
-    sp.res[k] = 0.0f;
+    if constexpr (SPT == 0) {
+      if (ok) sp.set_entry(k, s.u.st.cell[e], s.u.st.val[e]);
+    } else {
+      sp.set_entry(k, ok ? s.u.st.cell[e] : -1, ok ? s.u.st.val[e] : 0.0f);
+    }
   }
   __syncthreads();
   return mass;
@@ -509,7 +578,7 @@ __device__ __forceinline__ double build_support(PairSmem<D>& s, const float* __r
 // list, or (dense) 1 on every grid cell.  Writes mantissa and absolute log2
 // exponent to out_m / out_e.
 template <int D, int SPT, bool WEIGHTED>
-__device__ __forceinline__ void exact_chunk(PairSmem<D>& s, const Support<SPT>& xs, bool dense, int d, const int* Px,
+__device__ __forceinline__ void exact_chunk(PairSmem<D>& s, const SupList<SPT>& xs, bool dense, int d, const int* Px,
                                             const int* Qx, int base, int cnt, int* out_e, float* out_m) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int ti[XCHUNK], tj[XCHUNK], em[XCHUNK];
@@ -520,7 +589,7 @@ __device__ __forceinline__ void exact_chunk(PairSmem<D>& s, const Support<SPT>& 
     tj[t] = c % D;
     em[t] = QNONE;
   }
-  const int nd = dense ? (d * d + PWGS - 1) / PWGS : SPT;
+  const int nd = dense ? (d * d + PWGS - 1) / PWGS : xs.nk();
   for (int k = 0; k < nd; ++k) {
     int cell = -1;
     float x = 0.0f;
@@ -530,12 +599,15 @@ __device__ __forceinline__ void exact_chunk(PairSmem<D>& s, const Support<SPT>& 
         cell = (c / d) * D + (c % d);
         x = 1.0f;
       }
+    } else if constexpr (SPT == 0) {
+      cell = xs.cell(k);
+      if (cell >= 0) x = xs.res(k);
     } else {
 #pragma unroll
       for (int kk = 0; kk < SPT; ++kk)
         if (kk == k) {
-          cell = xs.cell[kk];
-          x = xs.res[kk];
+          cell = xs.cell(kk);
+          x = xs.res(kk);
         }
     }
     if (cell >= 0 && x > 0.0f) {
@@ -572,12 +644,15 @@ __device__ __forceinline__ void exact_chunk(PairSmem<D>& s, const Support<SPT>& 
         cell = (c / d) * D + (c % d);
         x = 1.0f;
       }
+    } else if constexpr (SPT == 0) {
+      cell = xs.cell(k);
+      if (cell >= 0) x = xs.res(k);
     } else {
 #pragma unroll
       for (int kk = 0; kk < SPT; ++kk)
         if (kk == k) {
-          cell = xs.cell[kk];
-          x = xs.res[kk];
+          cell = xs.cell(kk);
+          x = xs.res(kk);
         }
     }
     if (cell >= 0 && x > 0.0f) {
@@ -655,12 +730,12 @@ __device__ __forceinline__ int midrange(const int* mx, const int* mn, int r) { r
 // and the centre of the previous pass is read on the fly, so a half step
 // needs five workgroup barriers when no cell is suspect.
 template <int D, int SPT>
-__device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, bool wb_bf16, Support<SPT>& ys,
-                                         int (&q)[SPT], const Support<SPT>& xsup, bool x_dense, int d,
-                                         const Side& xs, int H, const int* Px, const int* Qx, int* Py, int* Qy,
-                                         bool out_bf16, bool clear_all, bool check, double& err_out, bool& stop_out,
-                                         ESum& dot, int& mres_out, int& bad, int& range, double errD, double m,
-                                         double tol, double switch_tol, bool& lowp, int t, int max_iter) {
+__device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, bool wb_bf16, SupList<SPT>& ys,
+                                         const SupList<SPT>& xsup, bool x_dense, int d, const Side& xs, int H,
+                                         const int* Px, const int* Qx, int* Py, int* Qy, bool out_bf16,
+                                         bool clear_all, bool check, double& err_out, bool& stop_out, ESum& dot,
+                                         int& mres_out, int& bad, int& range, double errD, double m, double tol,
+                                         double switch_tol, bool& lowp, int t, int max_iter) {
   constexpr int LDF = Cfg<D>::LDF;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const float mxf = (float)xs.mx;
@@ -670,49 +745,52 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, bool w
   // The X buffer can be cleared now (x was consumed by contraction 1) unless
   // an FP32 X overlaps the BF16 K x buffer still being read.
   const bool late_x = !out_bf16 && wb_bf16;
-  int qe[SPT];   // log2 estimate of the new y at the entry (QNONE: no entry)
+  const int nk = ys.nk();
 
   // Pass A: suspects, row extrema of sweep 0, error terms, X clearing.
   int lbad = 0, lover = 0;
   double eg = 0.0;
 #pragma unroll
-  for (int k = 0; k < SPT; ++k) {
-    q[k] = QNONE;
-    qe[k] = QNONE;
-    const int c = ys.cell[k];
+  for (int k = 0; k < nk; ++k) {
+    ys.set_q(k, QNONE);
+    ys.set_qe(k, QNONE);
+    const int c = ys.cell(k);
     if (c >= 0) {
       const int i = c / D, j = c % D;
       const float w = Wb[i * LDF + j];
+      const float tg = ys.tgt(k);
       const int dl = j - i + D - 1;
       const int E = xs.ex + s.tgde[dl] - s.R[i] - s.S[j];
       const float Dm = mxf * s.tgdm[dl];
       const int lw = w > 0.0f ? ilog2f(w) : QNONE;
       const int ld = Dm > 0.0f ? E + ilog2f(Dm) : QNONE;
       const int le = max(lw, ld);
+      int qk;
       bool sus = false;
       if (le < thr) {
         const int id = atomicAdd(&s.nsusp, 1);
         if (id < MAXSUSP) {
           s.susp_cell[id] = c;
-          q[k] = QSUSP + id;
+          qk = QSUSP + id;
           sus = true;
         } else {
           lover = 1;
           if (le == QNONE) lbad = 1;
-          q[k] = le == QNONE ? 0 : ilog2f(ys.tgt[k]) - le;
+          qk = le == QNONE ? 0 : ilog2f(tg) - le;
         }
       } else {
-        q[k] = ilog2f(ys.tgt[k]) - le;
+        qk = ilog2f(tg) - le;
       }
+      ys.set_q(k, qk);
       if (!sus) {
-        qe[k] = q[k];
-        atomicMax(&s.fit[0][0][i], q[k]);
-        atomicMin(&s.fit[0][1][i], q[k]);
+        ys.set_qe(k, qk);
+        atomicMax(&s.fit[0][0][i], qk);
+        atomicMin(&s.fit[0][1][i], qk);
         if (check) {
           const int sh = Py[i] + Qy[j] + s.R[i] + s.S[j];
-          const double row =
-              ldxd((double)ys.res[k] * (double)w, sh) + ldxd((double)ys.res[k] * (double)Dm, E + sh);
-          eg += fabs(row - (double)ys.tgt[k]);
+          const double r = (double)ys.res(k);
+          const double row = ldxd(r * (double)w, sh) + ldxd(r * (double)Dm, E + sh);
+          eg += fabs(row - (double)tg);
         }
       }
     }
@@ -721,9 +799,12 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, bool w
     if (clear_all) {
       zero_x<D>(s, out_bf16);
     } else {
+      const int xk = xsup.nk();
 #pragma unroll
-      for (int k = 0; k < SPT; ++k)
-        if (xsup.cell[k] >= 0) put_x<D>(s, xsup.cell[k], 0.0f, out_bf16);
+      for (int k = 0; k < xk; ++k) {
+        const int c = xsup.cell(k);
+        if (c >= 0) put_x<D>(s, c, 0.0f, out_bf16);
+      }
     }
   }
   {
@@ -766,17 +847,20 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, bool w
     __syncthreads();
     double eg2 = 0.0;
 #pragma unroll
-    for (int k = 0; k < SPT; ++k) {
-      if (q[k] >= QSUSP) {
-        const int id = q[k] - QSUSP;
-        const int c = ys.cell[k], i = c / D, j = c % D;
-        qe[k] = ilog2f(ys.tgt[k]) - (s.susp_e[id] + ilog2f(s.susp_m[id]));
-        atomicMax(&s.fit[0][0][i], qe[k]);
-        atomicMin(&s.fit[0][1][i], qe[k]);
+    for (int k = 0; k < nk; ++k) {
+      const int qk = ys.q(k);
+      if (qk >= QSUSP) {
+        const int id = qk - QSUSP;
+        const int c = ys.cell(k), i = c / D, j = c % D;
+        const float tg = ys.tgt(k);
+        const int qx = ilog2f(tg) - (s.susp_e[id] + ilog2f(s.susp_m[id]));
+        ys.set_qe(k, qx);
+        atomicMax(&s.fit[0][0][i], qx);
+        atomicMin(&s.fit[0][1][i], qx);
         if (check) {
           const int sh = Py[i] + Qy[j] + s.R[i] + s.S[j];
-          const double row = ldxd((double)ys.res[k] * (double)s.susp_m[id], s.susp_e[id] + sh);
-          eg2 += fabs(row - (double)ys.tgt[k]);
+          const double row = ldxd((double)ys.res(k) * (double)s.susp_m[id], s.susp_e[id] + sh);
+          eg2 += fabs(row - (double)tg);
         }
       }
     }
@@ -804,30 +888,33 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, bool w
   // Column extrema of sweep 0 (against the row centres of sweep 0), then the
   // rows and columns of sweep 1.
 #pragma unroll
-  for (int k = 0; k < SPT; ++k) {
-    if (qe[k] != QNONE) {
-      const int c = ys.cell[k], i = c / D, j = c % D;
-      const int v = qe[k] - midrange(s.fit[0][0], s.fit[0][1], i);
+  for (int k = 0; k < nk; ++k) {
+    const int qx = ys.qe(k);
+    if (qx != QNONE) {
+      const int c = ys.cell(k), i = c / D, j = c % D;
+      const int v = qx - midrange(s.fit[0][0], s.fit[0][1], i);
       atomicMax(&s.fit[0][2][j], v);
       atomicMin(&s.fit[0][3][j], v);
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < SPT; ++k) {
-    if (qe[k] != QNONE) {
-      const int c = ys.cell[k], i = c / D, j = c % D;
-      const int v = qe[k] - midrange(s.fit[0][2], s.fit[0][3], j);
+  for (int k = 0; k < nk; ++k) {
+    const int qx = ys.qe(k);
+    if (qx != QNONE) {
+      const int c = ys.cell(k), i = c / D, j = c % D;
+      const int v = qx - midrange(s.fit[0][2], s.fit[0][3], j);
       atomicMax(&s.fit[1][0][i], v);
       atomicMin(&s.fit[1][1][i], v);
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < SPT; ++k) {
-    if (qe[k] != QNONE) {
-      const int c = ys.cell[k], i = c / D, j = c % D;
-      const int v = qe[k] - midrange(s.fit[1][0], s.fit[1][1], i);
+  for (int k = 0; k < nk; ++k) {
+    const int qx = ys.qe(k);
+    if (qx != QNONE) {
+      const int c = ys.cell(k), i = c / D, j = c % D;
+      const int v = qx - midrange(s.fit[1][0], s.fit[1][1], i);
       atomicMax(&s.fit[1][2][j], v);
       atomicMin(&s.fit[1][3][j], v);
     }
@@ -842,25 +929,27 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, bool w
   ESum acc{NEG, 0.0};
   int maxres = 0;
 #pragma unroll
-  for (int k = 0; k < SPT; ++k) {
-    const int c = ys.cell[k];
+  for (int k = 0; k < nk; ++k) {
+    const int c = ys.cell(k);
     if (c >= 0) {
       const int i = c / D, j = c % D;
       const int dl = j - i + D - 1;
       const int rho = midrange(s.fit[1][0], s.fit[1][1], i), sig = midrange(s.fit[1][2], s.fit[1][3], j);
       const int sh = rho + sig;
+      const int qk = ys.q(k);
+      const float tg = ys.tgt(k);
       float y;
-      if (q[k] >= QSUSP) {
-        const int id = q[k] - QSUSP;
-        y = ys.tgt[k] / ldx(s.susp_m[id], s.susp_e[id] + sh);
+      if (qk >= QSUSP) {
+        const int id = qk - QSUSP;
+        y = tg / ldx(s.susp_m[id], s.susp_e[id] + sh);
       } else {
         const int E = xs.ex + s.tgde[dl] - s.R[i] - s.S[j];
         const float Dm = mxf * s.tgdm[dl];
-        y = ys.tgt[k] / (ldx(Wb[i * LDF + j], sh) + ldx(Dm, E + sh));
+        y = tg / (ldx(Wb[i * LDF + j], sh) + ldx(Dm, E + sh));
       }
-      ys.res[k] = y;
+      ys.set_res(k, y);
       if (!late_x) put_x<D>(s, c, y, out_bf16);
-      maxres = max(maxres, abs(qe[k] - sh));
+      maxres = max(maxres, abs(ys.qe(k) - sh));
       acc = esum_add(acc, ESum{rho - s.R[i] + sig - s.S[j] + s.tgde[dl], (double)y * (double)s.tgdm[dl]});
     }
   }
@@ -888,18 +977,31 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, bool w
     zero_x<D>(s, out_bf16);
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < SPT; ++k)
-      if (ys.cell[k] >= 0) put_x<D>(s, ys.cell[k], ys.res[k], out_bf16);
+    for (int k = 0; k < nk; ++k) {
+      const int c = ys.cell(k);
+      if (c >= 0) put_x<D>(s, c, ys.res(k), out_bf16);
+    }
   }
 }
 
+// Warm-start record of one pair's v (and its output after the solve):
+// residual on the grid cells (row stride D; only the cells of supp(b) are
+// read or written), row and column log2 scales, the diagonal entry
+// vmx * 2^vex and the residual span.
+template <int D>
+struct WarmState {
+  float vres[D * D];
+  int Pv[D];
+  int Qv[D];
+  int vex;
+  int mres;
+  double vmx;
+};
+
 template <int D, int SPT>
-__global__ __launch_bounds__(PWGS) void sinkhorn_pair_kernel(PairParams prm) {
-  __shared__ PairSmem<D> s;
+__device__ __forceinline__ void solve_pair(const PairParams& prm, PairSmem<D>& s, long long pair) {
   const int tid = threadIdx.x;
-  const long long pair = blockIdx.x;
   const int d = prm.d;
-  if (prm.only_redo && prm.redo[pair] != prm.only_redo) return;
 
   for (int x = tid; x < 2 * D; x += PWGS) {
     const bool in = x < 2 * D - 1;
@@ -913,7 +1015,16 @@ __global__ __launch_bounds__(PWGS) void sinkhorn_pair_kernel(PairParams prm) {
   }
   const float* __restrict__ A = prm.hist_a + (size_t)prm.ia[pair] * d * d;
   const float* __restrict__ B = prm.hist_b + (size_t)prm.ib[pair] * d * d;
-  Support<SPT> ua, vb;   // u on supp(a), v on supp(b)
+  SupList<SPT> ua, vb;   // u on supp(a), v on supp(b)
+  if constexpr (SPT == 0) {
+    int* base = reinterpret_cast<int*>(prm.lists + (size_t)blockIdx.x * prm.list_stride);
+    constexpr int CAP = D * D;
+    ua = SupList<0>{base, reinterpret_cast<float*>(base + CAP), reinterpret_cast<float*>(base + 2 * CAP),
+                    base + 3 * CAP, base + 4 * CAP, 0, CAP};
+    base += 5 * CAP;
+    vb = SupList<0>{base, reinterpret_cast<float*>(base + CAP), reinterpret_cast<float*>(base + 2 * CAP),
+                    base + 3 * CAP, base + 4 * CAP, 0, CAP};
+  }
   bool big_a, big_b, low_a, low_b;
   const double mA = build_support<D, SPT>(s, A, d, ua, big_a, low_a);
   const double mB = build_support<D, SPT>(s, B, d, vb, big_b, low_b);
@@ -934,36 +1045,62 @@ __global__ __launch_bounds__(PWGS) void sinkhorn_pair_kernel(PairParams prm) {
     }
     return;
   }
+  WarmState<D>* ws = prm.state ? reinterpret_cast<WarmState<D>*>(prm.state) + pair : nullptr;
+  const bool warm = ws && prm.state_in;
 
   bool lowp = prm.precision == 1;
-  int q[SPT];
-  // v = 1 on every grid cell and on the diagonal bin.
-  for (int r = tid; r < D; r += PWGS) {
-    s.Pv[r] = r < d ? 0 : NEG;
-    s.Qv[r] = r < d ? 0 : NEG;
-    s.Pu[r] = NEG;
-    s.Qu[r] = NEG;
-  }
+  const int nka = ua.nk(), nkb = vb.nk();
   ESum kv{NEG, 0.0};
+  Side su{0, 0.0, 0}, sv{0, 1.0, 0};
+  bool v_dense;   // v is the all-ones start (dense, not on supp(b))
   zero_x<D>(s, lowp);
-  __syncthreads();
-  for (int c = tid; c < d * d; c += PWGS) {
-    const int i = c / d, j = c % d;
-    put_x<D>(s, i * D + j, 1.0f, lowp);
-    kv = esum_add(kv, ESum{s.tgde[j - i + D - 1], (double)s.tgdm[j - i + D - 1]});
+  if (warm) {
+    // v from the previous solve of this pair (it lives on supp(b)).
+    for (int r = tid; r < D; r += PWGS) {
+      s.Pv[r] = ws->Pv[r];
+      s.Qv[r] = ws->Qv[r];
+      s.Pu[r] = NEG;
+      s.Qu[r] = NEG;
+    }
+    sv = Side{ws->vex, ws->vmx, ws->mres};
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < nkb; ++k) {
+      const int c = vb.cell(k);
+      if (c >= 0) {
+        const float r = ws->vres[c];
+        vb.set_res(k, r);
+        put_x<D>(s, c, r, lowp);
+        const int i = c / D, j = c % D, dl = j - i + D - 1;
+        kv = esum_add(kv, ESum{s.Pv[i] + s.Qv[j] + s.tgde[dl], (double)r * (double)s.tgdm[dl]});
+      }
+    }
+    v_dense = false;
+  } else {
+    // v = 1 on every grid cell and on the diagonal bin.
+    for (int r = tid; r < D; r += PWGS) {
+      s.Pv[r] = r < d ? 0 : NEG;
+      s.Qv[r] = r < d ? 0 : NEG;
+      s.Pu[r] = NEG;
+      s.Qu[r] = NEG;
+    }
+    __syncthreads();
+    for (int c = tid; c < d * d; c += PWGS) {
+      const int i = c / d, j = c % d;
+      put_x<D>(s, i * D + j, 1.0f, lowp);
+      kv = esum_add(kv, ESum{s.tgde[j - i + D - 1], (double)s.tgdm[j - i + D - 1]});
+    }
+#pragma unroll
+    for (int k = 0; k < nkb; ++k) vb.set_res(k, 1.0f);
+    v_dense = true;
   }
 #pragma unroll
-  for (int k = 0; k < SPT; ++k) {
-    q[k] = QNONE;
-    vb.res[k] = 1.0f;
-  }
-  Side su{0, 0.0, 0}, sv{0, 1.0, 0};
-  kv = esum_add(block_esum<PNW>(kv, s.rede, s.reds), ESum{0, 1.0});   // (K v)_Delta = <v, k_Delta> + v_Delta
+  for (int k = 0; k < nka; ++k) ua.set_q(k, QNONE);
+  kv = esum_add(block_esum<PNW>(kv, s.rede, s.reds), ESum{sv.ex, sv.mx});   // (K v)_Delta = <v, k_Delta> + v_Delta
   ESum ku{NEG, 0.0};
 
   int t = 0, it_lp = 0, it_hp = 0, bad = 0, range = 0;
   bool x_lp = lowp;      // format of the residual currently in the X buffer
-  bool v_dense = true;   // v is still the all-ones start (dense, not on supp(b))
   double err = INFINITY;
   __syncthreads();
   for (;;) {
@@ -974,7 +1111,7 @@ __global__ __launch_bounds__(PWGS) void sinkhorn_pair_kernel(PairParams prm) {
     bool stop = false;
     ESum dotu;
     const double errD = (t >= 1) ? fabs(ldxd(su.mx * kv.s, su.ex + kv.e) - aD) : 0.0;
-    y_update<D, SPT>(s, Wb, lp_now, ua, q, vb, v_dense, d, sv, Hv, s.Pv, s.Qv, s.Pu, s.Qu, lp_now,
+    y_update<D, SPT>(s, Wb, lp_now, ua, vb, v_dense, d, sv, Hv, s.Pv, s.Qv, s.Pu, s.Qu, lp_now,
                      v_dense || x_lp != lp_now, t >= 1, err, stop, dotu, su.mres, bad, range, errD, m, prm.tol,
                      prm.switch_tol, lowp, t, prm.max_iter);
     if (stop || bad) break;
@@ -989,12 +1126,9 @@ __global__ __launch_bounds__(PWGS) void sinkhorn_pair_kernel(PairParams prm) {
     ESum dotv;
     bool nostop = false;
     double dummy = 0.0;
-    {
-      int qv[SPT];
-      y_update<D, SPT>(s, Wb, lp_now, vb, qv, ua, false, d, su, Hu, s.Pu, s.Qu, s.Pv, s.Qv, lowp, x_lp != lowp, false,
-                       dummy, nostop, dotv, sv.mres, bad, range, 0.0, m, prm.tol, prm.switch_tol, lowp, t,
-                       prm.max_iter);
-    }
+    y_update<D, SPT>(s, Wb, lp_now, vb, ua, false, d, su, Hu, s.Pu, s.Qu, s.Pv, s.Qv, lowp, x_lp != lowp, false,
+                     dummy, nostop, dotv, sv.mres, bad, range, 0.0, m, prm.tol, prm.switch_tol, lowp, t,
+                     prm.max_iter);
     v_dense = false;
     x_lp = lowp;
     sv.ex = -ku.e;
@@ -1019,8 +1153,10 @@ __global__ __launch_bounds__(PWGS) void sinkhorn_pair_kernel(PairParams prm) {
     for (int c = tid; c < d * d; c += PWGS) put_x<D>(s, (c / d) * D + (c % d), 1.0f, false);
   } else {
 #pragma unroll
-    for (int k = 0; k < SPT; ++k)
-      if (vb.cell[k] >= 0) put_x<D>(s, vb.cell[k], vb.res[k], false);
+    for (int k = 0; k < nkb; ++k) {
+      const int c = vb.cell(k);
+      if (c >= 0) put_x<D>(s, c, vb.res(k), false);
+    }
   }
   __syncthreads();
   double g = 0.0;
@@ -1032,11 +1168,14 @@ __global__ __launch_bounds__(PWGS) void sinkhorn_pair_kernel(PairParams prm) {
     if (pass == 0) gemm_kt<D, false, true>(s, s.Pv, Wf, tri);
     else gemm_kt<D, false, false>(s, s.Pv, Wf, tri);
 #pragma unroll
-    for (int k = 0; k < SPT; ++k) {
-      const int c = ua.cell[k];
-      if (c >= 0 && ua.res[k] > 0.0f && q[k] < QSUSP) {
-        const int i = c / D, j = c % D;
-        g += ldxd((double)ua.res[k] * (double)Wf[i * Cfg<D>::LDF + j], s.Pu[i] + s.Qu[j] + s.R[i] + s.S[j]);
+    for (int k = 0; k < nka; ++k) {
+      const int c = ua.cell(k);
+      if (c >= 0 && ua.q(k) < QSUSP) {
+        const float r = ua.res(k);
+        if (r > 0.0f) {
+          const int i = c / D, j = c % D;
+          g += ldxd((double)r * (double)Wf[i * Cfg<D>::LDF + j], s.Pu[i] + s.Qu[j] + s.R[i] + s.S[j]);
+        }
       }
     }
     __syncthreads();
@@ -1047,25 +1186,55 @@ __global__ __launch_bounds__(PWGS) void sinkhorn_pair_kernel(PairParams prm) {
       exact_chunk<D, SPT, true>(s, vb, v_dense, d, s.Pv, s.Qv, base, min(XCHUNK, ns - base), s.susp_e + base,
                                 s.susp_m + base);
 #pragma unroll
-    for (int k = 0; k < SPT; ++k) {
-      if (q[k] >= QSUSP && ua.res[k] > 0.0f) {
-        const int c = ua.cell[k], i = c / D, j = c % D;
-        const int id = q[k] - QSUSP;
-        g += ldxd((double)ua.res[k] * (double)s.susp_m[id], s.susp_e[id] + s.Pu[i] + s.Qu[j]);
+    for (int k = 0; k < nka; ++k) {
+      const int qk = ua.q(k);
+      if (qk >= QSUSP) {
+        const float r = ua.res(k);
+        if (r > 0.0f) {
+          const int c = ua.cell(k), i = c / D, j = c % D;
+          const int id = qk - QSUSP;
+          g += ldxd((double)r * (double)s.susp_m[id], s.susp_e[id] + s.Pu[i] + s.Qu[j]);
+        }
+      }
+    }
+  }
+  const double lnvD = log(sv.mx) + (double)sv.ex * 0.69314718055994530942;   // log v_Delta
+#pragma unroll
+  for (int k = 0; k < nka; ++k) {
+    const int c = ua.cell(k);
+    if (c >= 0) {
+      const float r = ua.res(k);
+      const int i = c / D, j = c % D, dl = j - i + D - 1;
+      if (r > 0.0f)
+        g += ldxd(sv.mx * (double)r * (double)s.tgdm[dl] * (double)s.tcd[dl], sv.ex + s.Pu[i] + s.Qu[j] + s.tgde[dl]);
+      if (prm.gout) {
+        // gradient term of Proposition 5 at this cell: log u + log v_Delta
+        const double lu = r > 0.0f ? (log((double)r) + (double)(s.Pu[i] + s.Qu[j]) * 0.69314718055994530942) : 0.0;
+        prm.gout[(size_t)pair * d * d + i * d + j] = lu + lnvD;
       }
     }
   }
 #pragma unroll
-  for (int k = 0; k < SPT; ++k) {
-    if (ua.cell[k] >= 0 && ua.res[k] > 0.0f) {
-      const int c = ua.cell[k], i = c / D, j = c % D, dl = j - i + D - 1;
-      g += ldxd(sv.mx * (double)ua.res[k] * (double)s.tgdm[dl] * (double)s.tcd[dl],
-                sv.ex + s.Pu[i] + s.Qu[j] + s.tgde[dl]);
+  for (int k = 0; k < nkb; ++k) {
+    const int c = vb.cell(k);
+    if (c >= 0) {
+      const float r = vb.res(k);
+      if (!v_dense && r > 0.0f) {
+        const int i = c / D, j = c % D, dl = j - i + D - 1;
+        g += ldxd(su.mx * (double)r * (double)s.tgdm[dl] * (double)s.tcd[dl], su.ex + s.Pv[i] + s.Qv[j] + s.tgde[dl]);
+      }
+      if (ws && !v_dense) ws->vres[c] = r;
     }
-    if (!v_dense && vb.cell[k] >= 0 && vb.res[k] > 0.0f) {
-      const int c = vb.cell[k], i = c / D, j = c % D, dl = j - i + D - 1;
-      g += ldxd(su.mx * (double)vb.res[k] * (double)s.tgdm[dl] * (double)s.tcd[dl],
-                su.ex + s.Pv[i] + s.Qv[j] + s.tgde[dl]);
+  }
+  if (ws && !v_dense) {
+    for (int r = tid; r < D; r += PWGS) {
+      ws->Pv[r] = s.Pv[r];
+      ws->Qv[r] = s.Qv[r];
+    }
+    if (tid == 0) {
+      ws->vex = sv.ex;
+      ws->vmx = sv.mx;
+      ws->mres = sv.mres;
     }
   }
   const double cost = block_sum<PNW>(g, s.red);
@@ -1079,6 +1248,24 @@ __global__ __launch_bounds__(PWGS) void sinkhorn_pair_kernel(PairParams prm) {
     prm.iters[2 * pair + 1] = it_hp;
     prm.err[pair] = (float)err;
     prm.status[pair] = st;
+  }
+}
+
+// One workgroup per pair; the grid may be smaller than the batch (global-list
+// variant), in which case each workgroup takes pairs blockIdx.x, + gridDim.x, ...
+template <int D, int SPT>
+__global__ __launch_bounds__(PWGS) void sinkhorn_pair_kernel(PairParams prm) {
+  __shared__ PairSmem<D> s;
+  if constexpr (SPT > 0) {   // one pair per workgroup
+    const long long pair = blockIdx.x;
+    if (prm.only_redo && prm.redo[pair] != prm.only_redo) return;
+    solve_pair<D, SPT>(prm, s, pair);
+  } else {
+    for (long long pair = blockIdx.x; pair < prm.n_pairs; pair += gridDim.x) {
+      if (prm.only_redo && prm.redo[pair] != prm.only_redo) continue;
+      solve_pair<D, SPT>(prm, s, pair);
+      __syncthreads();
+    }
   }
 }
 

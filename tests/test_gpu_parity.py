@@ -12,7 +12,7 @@ import pytest
 import torch
 
 import pdgen
-from oracle import ground, kmeans, sinkhorn
+from oracle import barycenter, ground, kmeans, sinkhorn
 
 pytestmark = pytest.mark.gpu
 
@@ -224,3 +224,37 @@ def test_kmeans_assign_matches_oracle(pds):
             assert assign[n] == ol[n]
         else:
             assert dist[n, assign[n]] <= dist[n].min() * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("d,g,lo,hi", [(16, 1e-2, 10, 40), (40, 5e-3, 20, 80)])
+def test_barycenter_matches_oracle(pds, d, g, lo, hi):
+    """Algorithm 2, four outer steps with warm-started inner solves to 1e-6:
+    energy to 1e-5 relative and z cell by cell against the FP64 oracle.  At
+    d = 40 the barycenter's support (820 cells) runs in the global-list
+    variant; at d = 16 in registers."""
+    diags = pdgen.bary_set(7, n_diag=4, lo=lo, hi=hi, template_size=60)
+    hists = [ground.discretize(x, d) for x in diags]
+    ob = barycenter.barycenter(hists, g, lam=5.0, tol=1e-6, max_inner=50000, max_outer=4, energy_rtol=0.0,
+                               C=dense_C(d))
+    with pds.Context(d, g, tol=1e-6, max_iter=50000) as ctx:
+        H = torch.from_numpy(np.stack(hists).astype(np.float32)).cuda()
+        z, E, outer = pds.pd_barycenter(ctx, H, lam=5.0, max_outer=4, energy_rtol=0.0)
+        z = z.cpu().numpy()
+    assert outer == ob.outer == 4
+    assert rel(E, ob.energy) <= 1e-5, (E, ob.energy)
+    np.testing.assert_allclose(z, ob.z, rtol=1e-4, atol=1e-6 * ob.z.max())
+
+
+def test_barycenter_energy_stop(pds):
+    """The outer loop stops at the first step whose relative energy change is
+    below energy_rtol, as the oracle does."""
+    d, g = 16, 1e-2
+    diags = pdgen.bary_set(3, n_diag=3, lo=10, hi=30, template_size=40)
+    hists = [ground.discretize(x, d) for x in diags]
+    ob = barycenter.barycenter(hists, g, lam=5.0, tol=1e-6, max_inner=50000, max_outer=30, energy_rtol=0.01,
+                               C=dense_C(d))
+    with pds.Context(d, g, tol=1e-6, max_iter=50000) as ctx:
+        H = torch.from_numpy(np.stack(hists).astype(np.float32)).cuda()
+        z, E, outer = pds.pd_barycenter(ctx, H, lam=5.0, max_outer=30, energy_rtol=0.01)
+    assert outer == ob.outer and ob.outer < 30
+    assert rel(E, ob.energy) <= 1e-5
