@@ -136,7 +136,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", choices=["bf16", "fp32"], default=None, help="run one precision only")
-    ap.add_argument("--switch-tol", type=float, default=1.5e-3)
+    ap.add_argument("--switch-tol", type=float, default=1.1e-3,
+                    help="BF16 -> FP32 switch point of the marginal error (1.1 x tol)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -174,7 +175,8 @@ def main():
                                 "max": int(ipp.max())}
         print(f"[{prec}] {r['iters_total']} pair-iterations per step, kernel {k_avg * 1e3:.2f} ms, "
               f"{r['kernel_pair_it_per_s']:.3e} pair-it/s, {r['achieved_tflops']:.1f} TFLOP/s, "
-              f"bad status {r['n_bad_status']}, iterations per pair {r['iters_quantiles']}",
+              f"bad status {r['n_bad_status']}, iterations per pair {r['iters_quantiles']} "
+              f"(bf16 {r['iters_bf16']}, fp32 {r['iters_fp32']})",
               file=sys.stderr, flush=True)
 
     main_key = "bf16" if "bf16" in res else "fp32"

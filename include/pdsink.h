@@ -61,7 +61,8 @@ typedef struct {
   double  tol;          /* stop when (||P1-a||_1 + |.|_Delta)/m <= tol; 0 = run max_iter */
   int32_t max_iter;     /* cap on full (u, v) iterations, >= 1                         */
   int32_t precision;    /* PDSINK_FP32 or PDSINK_BF16_REFINE                           */
-  double  switch_tol;   /* BF16_REFINE: switch to FP32 once err <= switch_tol          */
+  double  switch_tol;   /* BF16_REFINE: switch to FP32 once err <= switch_tol (or after
+                         * max_iter / 2 iterations); stopping is decided in FP32 only */
 } pdsink_params;
 
 /* Create a context for `params` on HIP device `device`: validates the
@@ -155,6 +156,26 @@ int kmeans_assign(pdsink_ctx* ctx, int64_t n_diag, const float* hist,
                   int32_t k, const float* centroids,
                   int32_t* assign, double* dist, int32_t* status,
                   void* ws, size_t ws_bytes, void* stream);
+
+/* k-means (section 5) by Lloyd rounds.  Each round assigns every diagram to
+ * its nearest centroid (as kmeans_assign) and then replaces each centroid that
+ * has members by the Algorithm 2 barycenter of its members, started from the
+ * uniform measure (as pd_barycenter with init_uniform); a centroid without
+ * members is kept.
+ *   hist      (device) float32 [n_diag, d, d]
+ *   init      (host)   int32   [k]  indices of the initial centroids, distinct, in [0, n_diag)
+ *   centroids (device) float32 [k, d, d]  out: centroids after the last round
+ *   assign    (device) int32   [n_diag]   out: the last round's assignment
+ *   objective (host)   double  [rounds]   out, may be NULL: per round, the sum over
+ *             the diagrams of the distance to the assigned centroid
+ *   ws, ws_bytes (device) at least pdsink_lloyd_workspace_bytes(n_diag, k)
+ * Synchronises `stream` once per round and per barycenter outer step.
+ * PDSINK_ERANGE if a distance or barycenter step is not finite. */
+int pdsink_lloyd_workspace_bytes(const pdsink_ctx* ctx, int64_t n_diag, int32_t k, size_t* bytes);
+int kmeans_lloyd(pdsink_ctx* ctx, int64_t n_diag, const float* hist, int32_t k, const int32_t* init,
+                 int32_t rounds, double lambda, int32_t max_outer, double energy_rtol,
+                 float* centroids, int32_t* assign, double* objective,
+                 void* ws, size_t ws_bytes, void* stream);
 
 /* Static string for a PDSINK_* return code. */
 const char* pdsink_strerror(int code);

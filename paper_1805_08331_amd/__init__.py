@@ -15,6 +15,7 @@ from __future__ import annotations
 import ctypes
 from dataclasses import dataclass
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -196,3 +197,28 @@ def pd_barycenter(ctx: Context, hist: torch.Tensor, lam: float = 5.0, max_outer:
         ctx.handle, n, _vp(hist), float(lam), int(max_outer), float(energy_rtol), int(init), _vp(z),
         ctypes.byref(energy), ctypes.byref(outer), _vp(ws), ws.numel(), _stream()))
     return z, float(energy.value), int(outer.value)
+
+
+def kmeans_lloyd(ctx: Context, hist: torch.Tensor, k: int, rounds: int, init, lam: float = 5.0,
+                 max_outer: int = 10, energy_rtol: float = 0.01):
+    """k-means by Lloyd rounds (section 5).  ``init``: k distinct diagram
+    indices of the initial centroids (a seeded draw made by the caller).
+    Returns ``(centroids [k, d, d], assign [n], objective [rounds] numpy)``."""
+    dev = ctx.device
+    _need(hist, "hist", torch.float32, dev)
+    n = hist.shape[0]
+    init = np.ascontiguousarray(np.asarray(init, dtype=np.int32))
+    if init.shape != (k,):
+        raise ValueError("init must hold k indices")
+    cents = torch.empty((k, ctx.d, ctx.d), dtype=torch.float32, device=dev)
+    assign = torch.empty((n,), dtype=torch.int32, device=dev)
+    obj = np.zeros(max(rounds, 1), dtype=np.float64)
+    nb = ctypes.c_size_t()
+    lib = _lib.load()
+    _lib.check("pdsink_lloyd_workspace_bytes", lib.pdsink_lloyd_workspace_bytes(ctx.handle, n, k, ctypes.byref(nb)))
+    ws = torch.empty(max(nb.value, 1), dtype=torch.uint8, device=dev)
+    _lib.check("kmeans_lloyd", lib.kmeans_lloyd(
+        ctx.handle, n, _vp(hist), int(k), init.ctypes.data_as(ctypes.c_void_p), int(rounds), float(lam),
+        int(max_outer), float(energy_rtol), _vp(cents), _vp(assign), obj.ctypes.data_as(ctypes.c_void_p), _vp(ws),
+        ws.numel(), _stream()))
+    return cents, assign, obj[:rounds]

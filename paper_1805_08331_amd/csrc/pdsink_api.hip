@@ -252,6 +252,14 @@ __global__ void bary_step_kernel(const double* __restrict__ gout, int64_t n, int
   z[c] = (float)((double)zc * exp(-scale * gsum));
 }
 
+// out[m] = hist[idx[m]] (d * d floats each).
+__global__ void gather_hist_kernel(const float* __restrict__ hist, const int32_t* __restrict__ idx, int dd,
+                                   float* __restrict__ out) {
+  const int64_t m = blockIdx.y;
+  const float* src = hist + (int64_t)idx[m] * dd;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < dd; c += gridDim.x * blockDim.x) out[m * dd + c] = src[c];
+}
+
 extern "C" {
 
 const char* pdsink_strerror(int code) {
@@ -517,6 +525,89 @@ int pd_barycenter(pdsink_ctx* ctx, int64_t n_diag, const float* hist, double lam
   }
   *energy = E;
   *outer = t + 1;
+  return PDSINK_OK;
+}
+
+int pdsink_lloyd_workspace_bytes(const pdsink_ctx* ctx, int64_t n_diag, int32_t k, size_t* bytes) {
+  if (!ctx || !bytes || n_diag < 0 || k < 1) return PDSINK_EINVAL;
+  const int64_t dd = (int64_t)ctx->prm.d * ctx->prm.d;
+  size_t kw = 0, bw = 0;
+  pdsink_workspace_bytes(ctx, PDSINK_OP_KMEANS, n_diag * k, &kw);
+  pdsink_workspace_bytes(ctx, PDSINK_OP_BARYCENTER, n_diag, &bw);
+  *bytes = align256(kw) + align256(n_diag * k * 8) + align256(n_diag * 4) + align256(n_diag * dd * 4) + bw;
+  return PDSINK_OK;
+}
+
+int kmeans_lloyd(pdsink_ctx* ctx, int64_t n_diag, const float* hist, int32_t k, const int32_t* init, int32_t rounds,
+                 double lambda, int32_t max_outer, double energy_rtol, float* centroids, int32_t* assign,
+                 double* objective, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx || n_diag < 1 || k < 1 || k > n_diag || !hist || !init || rounds < 0 || !centroids || !assign ||
+      max_outer < 1 || (int64_t)n_diag * k > INT_MAX)
+    return PDSINK_EINVAL;
+  for (int c = 0; c < k; ++c) {
+    if (init[c] < 0 || init[c] >= n_diag) return PDSINK_EINVAL;
+    for (int e = 0; e < c; ++e)
+      if (init[e] == init[c]) return PDSINK_EINVAL;
+  }
+  size_t need = 0;
+  pdsink_lloyd_workspace_bytes(ctx, n_diag, k, &need);
+  if (!ws || ws_bytes < need) return PDSINK_ENOMEM;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return PDSINK_EDEVICE;
+  const int64_t dd = (int64_t)ctx->prm.d * ctx->prm.d;
+  size_t kw = 0, bw = 0;
+  pdsink_workspace_bytes(ctx, PDSINK_OP_KMEANS, n_diag * k, &kw);
+  pdsink_workspace_bytes(ctx, PDSINK_OP_BARYCENTER, n_diag, &bw);
+  char* w = (char*)ws;
+  char* kws = w;
+  w += align256(kw);
+  double* dist = (double*)w;
+  w += align256(n_diag * k * 8);
+  int32_t* midx = (int32_t*)w;
+  w += align256(n_diag * 4);
+  float* memb = (float*)w;
+  w += align256(n_diag * dd * 4);
+  char* bws = w;
+  hipStream_t s = (hipStream_t)stream;
+  for (int c = 0; c < k; ++c)
+    if (hipMemcpyAsync(centroids + c * dd, hist + (int64_t)init[c] * dd, dd * 4, hipMemcpyDeviceToDevice, s) !=
+        hipSuccess)
+      return PDSINK_EDEVICE;
+  std::vector<int32_t> ha(n_diag), members;
+  std::vector<double> hd(n_diag * k);
+  members.reserve(n_diag);
+  for (int r = 0; r < rounds; ++r) {
+    int rc = kmeans_assign(ctx, n_diag, hist, k, centroids, assign, dist, nullptr, kws, kw, stream);
+    if (rc) return rc;
+    if (hipMemcpyAsync(ha.data(), assign, n_diag * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(hd.data(), dist, n_diag * k * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return PDSINK_EDEVICE;
+    double obj = 0.0;
+    for (int64_t n = 0; n < n_diag; ++n) obj += hd[n * k + ha[n]];
+    if (!std::isfinite(obj)) return PDSINK_ERANGE;
+    if (objective) objective[r] = obj;
+    for (int c = 0; c < k; ++c) {
+      members.clear();
+      for (int64_t n = 0; n < n_diag; ++n)
+        if (ha[n] == c) members.push_back((int32_t)n);
+      if (members.empty()) continue;
+      const int64_t m = (int64_t)members.size();
+      if (hipMemcpyAsync(midx, members.data(), m * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return PDSINK_EDEVICE;
+      hipLaunchKernelGGL(gather_hist_kernel, dim3((unsigned)((dd + 255) / 256), (unsigned)m), dim3(256), 0, s, hist,
+                         midx, (int)dd, memb);
+      if ((rc = last_error())) return rc;
+      double E = 0.0;
+      int32_t outer = 0;
+      size_t bneed = 0;
+      pdsink_workspace_bytes(ctx, PDSINK_OP_BARYCENTER, m, &bneed);
+      rc = pd_barycenter(ctx, m, memb, lambda, max_outer, energy_rtol, 1, centroids + c * dd, &E, &outer, bws, bneed,
+                         stream);
+      if (rc) return rc;
+    }
+  }
   return PDSINK_OK;
 }
 

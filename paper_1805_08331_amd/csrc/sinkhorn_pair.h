@@ -244,15 +244,18 @@ __device__ __forceinline__ float kentry(const PairSmem<D>& s, int i, int k, cons
 // pattern by adding the exponent shift to the table word; results below the
 // smallest normal BF16 (2^-126, at least 2^-166 below the row maximum) are 0.
 template <int D>
-__device__ __forceinline__ void build_kernels_bf16(PairSmem<D>& s, const int* P, const int* Q) {
+__device__ __forceinline__ void build_kernels_bf16(PairSmem<D>& s, const int* P, const int* Q, int d) {
   constexpr int LDB = Cfg<D>::LDB;
-  constexpr int NCH = D / 16;             // 16-entry chunks per row
-  // item = ((side * NCH + chunk) * D + row): adjacent lanes take adjacent rows
+  // Rows i >= d feed only output rows/columns that are never read, so they
+  // are skipped; chunks of columns k >= d hold exact zeros (P_k = NEG) and
+  // are written without table reads.
+  const int nch = (d + 15) / 16;          // 16-entry chunks per row that touch k < d
+  // item = ((side * nch + chunk) * d + row): adjacent lanes take adjacent rows
   // of one chunk, so their table reads hit adjacent LDS banks.
-  for (int item = threadIdx.x; item < 2 * NCH * D; item += PWGS) {
-    const int i = item % D, sc = item / D;
-    const bool first = sc < NCH;
-    const int k0 = 16 * (first ? sc : sc - NCH);
+  for (int item = threadIdx.x; item < 2 * nch * d; item += PWGS) {
+    const int i = item % d, sc = item / d;
+    const bool first = sc < nch;
+    const int k0 = 16 * (first ? sc : sc - nch);
     const int* X = (first ? P : Q) + k0;
     const int base = 126 - (first ? s.R : s.S)[i];
     const int* tw = s.tkb + i - k0 + D - 1;    // tw[-t] = word of delta = i - (k0 + t)
@@ -273,6 +276,15 @@ __device__ __forceinline__ void build_kernels_bf16(PairSmem<D>& s, const int* P,
     uint4* dst = reinterpret_cast<uint4*>((first ? s.u.b.K1 : s.u.b.K2) + i * LDB + k0);
     dst[0] = uint4{pk[0], pk[1], pk[2], pk[3]};
     dst[1] = uint4{pk[4], pk[5], pk[6], pk[7]};
+  }
+  const int nz = D / 16 - nch;            // all-zero chunks per row
+  for (int item = threadIdx.x; item < 2 * nz * d; item += PWGS) {
+    const int i = item % d, sc = item / d;
+    const bool first = sc < nz;
+    const int k0 = 16 * (nch + (first ? sc : sc - nz));
+    uint4* dst = reinterpret_cast<uint4*>((first ? s.u.b.K1 : s.u.b.K2) + i * LDB + k0);
+    dst[0] = uint4{0u, 0u, 0u, 0u};
+    dst[1] = uint4{0u, 0u, 0u, 0u};
   }
 }
 
@@ -427,7 +439,7 @@ __device__ __forceinline__ float* apply_K(PairSmem<D>& s, const int* P, const in
   __syncthreads();
   float* Wb = wbuf<D>(s, lowp);
   if (lowp) {
-    build_kernels_bf16<D>(s, P, Q);
+    build_kernels_bf16<D>(s, P, Q, d);
     __syncthreads();
     gemm_xk<D, true, false>(s, Q, trim);
     __syncthreads();
@@ -875,7 +887,10 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, bool w
   if (check) {
     err_out = (egs + errD) / m;
     const bool measured_lowp = lowp;   // never stop on an error measured with BF16 contractions
-    if (lowp && err_out <= switch_tol) lowp = false;
+    // BF16 ends at switch_tol, or at half the iteration budget whatever the
+    // error, so that a pair whose BF16 error floor lies above switch_tol still
+    // finishes in FP32.
+    if (lowp && (err_out <= switch_tol || 2 * t >= max_iter)) lowp = false;
     if ((!measured_lowp && err_out <= tol) || t >= max_iter) {
       stop_out = true;
       if (flags & 1) bad = 1;

@@ -258,3 +258,23 @@ def test_barycenter_energy_stop(pds):
         z, E, outer = pds.pd_barycenter(ctx, H, lam=5.0, max_outer=30, energy_rtol=0.01)
     assert outer == ob.outer and ob.outer < 30
     assert rel(E, ob.energy) <= 1e-5
+
+
+def test_kmeans_lloyd_matches_oracle(pds):
+    """Two Lloyd rounds (assignment, then barycenters of the members from the
+    uniform start) against the oracle: labels, per-round objective, centroids."""
+    d, g = 16, 1e-2
+    diags, _ = pdgen.kmeans_set(5, 12, n_templates=3, template_size=20)
+    hists = [ground.discretize(x, d) for x in diags]
+    init = np.random.default_rng(0).choice(len(hists), size=3, replace=False)
+    cents, labels, hist_obj = kmeans.lloyd(hists, 3, 2, g, tol=1e-6, seed=0, lam=5.0, max_outer=4,
+                                           energy_rtol=0.01, C=dense_C(d))
+    with pds.Context(d, g, tol=1e-6, max_iter=50000) as ctx:
+        H = torch.from_numpy(np.stack(hists).astype(np.float32)).cuda()
+        zc, assign, obj = pds.kmeans_lloyd(ctx, H, 3, 2, init, lam=5.0, max_outer=4, energy_rtol=0.01)
+        zc = zc.cpu().numpy()
+        assign = assign.cpu().numpy()
+    np.testing.assert_array_equal(assign, labels)
+    np.testing.assert_allclose(obj, hist_obj, rtol=1e-5)
+    for c in range(3):
+        np.testing.assert_allclose(zc[c], cents[c], rtol=1e-4, atol=1e-6 * cents[c].max())
