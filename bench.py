@@ -129,6 +129,51 @@ def cpu_baseline(budget_s: float = 20.0):
                       f"os.cpu_count()={os.cpu_count()}"}
 
 
+def pmc_probe(pts_d, off_d, switch_tol: float, copy_mib: int = 256):
+    """One BF16 batch and one plain device copy of known size, for counter runs
+    (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE): the copy calibrates the
+    counters' byte scale."""
+    import torch
+    import paper_1805_08331_amd as pds
+
+    ctx = pds.Context(D, GAMMA, tol=TOL, max_iter=5000, precision="bf16", switch_tol=switch_tol)
+    hist, mass, nbad = pds.pd_discretize(ctx, pts_d, off_d)
+    n = NPAIRS
+    ia = torch.arange(0, n, dtype=torch.int32, device=ctx.device)
+    ib = torch.arange(n, 2 * n, dtype=torch.int32, device=ctx.device)
+    pds.sinkhorn_dist_batch(ctx, hist, hist, ia, ib)
+    src = torch.ones(copy_mib << 18, dtype=torch.float32, device=ctx.device)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ctx.close()
+    print(json.dumps({"pmc_probe": True, "copy_bytes": copy_mib << 20, "pairs": n}))
+
+
+def source_hash() -> str:
+    """Hash of the kernel sources: counter figures apply only to the build they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1805_08331_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".h", ".hip")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the pair kernel from the committed counter summary,
+    or None when the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "sinkhorn_pair_kernel_d100_1024pairs_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    return rec.get("traffic_bytes") if rec.get("source_hash") == source_hash() else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,6 +181,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", choices=["bf16", "fp32"], default=None, help="run one precision only")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="run one BF16 batch and a 256 MiB device copy (for counter runs), then exit")
     ap.add_argument("--switch-tol", type=float, default=1.1e-3,
                     help="BF16 -> FP32 switch point of the marginal error (1.1 x tol)")
     args = ap.parse_args()
@@ -151,6 +198,10 @@ def main():
     pts, off = pdgen.to_csr(d1 + d2)
     pts_d = torch.from_numpy(pts).cuda()
     off_d = torch.from_numpy(off).cuda()
+
+    if args.pmc_probe:
+        pmc_probe(pts_d, off_d, args.switch_tol)
+        return
 
     res = {}
     for prec in (["bf16", "fp32"] if args.only is None else [args.only]):
@@ -205,7 +256,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(m["step_ms"], 50)), "p99": float(np.percentile(m["step_ms"], 99)),
                        "of": "one 1024-pair batch (discretise + Algorithm 1 + cost)"},
         "roofline": {"bound": "mfma", "achieved": m["achieved_tflops"], "peak": m["peak_tflops"], "unit": "TFLOP/s",
-                     "frac": m["achieved_tflops"] / m["peak_tflops"], "traffic": None,
+                     "frac": m["achieved_tflops"] / m["peak_tflops"], "traffic": measured_traffic(),
                      "kernel": "sinkhorn_pair_kernel<128, 1>", "kernel_ms": k_avg * 1e3},
     }
     if "fp32" in res and main_key == "bf16":

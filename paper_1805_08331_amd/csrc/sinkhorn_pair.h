@@ -379,50 +379,75 @@ __device__ __forceinline__ void gemm_xk(PairSmem<D>& s, const int* Q, bool trim)
 // Contraction 2 for the calling wave's tiles (ti, tj); after every wave has
 // read T, the tiles go to the K x buffer Wb:
 //   W[i][j] = sum_k kt1[i][k] * T[k][j]   (kt1 times c1 when WEIGHTED)
-// With `tri`, only tiles on or above the diagonal are computed.
+// With `tri`, only tiles on or above the diagonal are computed.  Each wave
+// runs two independent accumulation chains so that its matrix-core work
+// overlaps with the operand reads: its two tiles side by side, or, with one
+// tile, the two halves of the k range (added at the end).
 template <int D, bool BF16, bool WEIGHTED>
 __device__ __forceinline__ void gemm_kt(PairSmem<D>& s, const int* P, float* Wb, bool tri) {
   constexpr int LDF = Cfg<D>::LDF, LDB = Cfg<D>::LDB;
-  constexpr int TPW = (Cfg<D>::NTILES + PNW - 1) / PNW;
   const int lane = threadIdx.x & 63, lr = lane & 31, lk = lane >> 5;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave index, held in a scalar register
-  floatx16 acc[TPW];
-  bool has[TPW];
-  int tis[TPW], tjs[TPW];
-#pragma unroll
-  for (int u = 0; u < TPW; ++u) {
-    acc[u] = floatx16{};
-    has[u] = kt_tile<D>(w, u, tri, tis[u], tjs[u]);
-    if (has[u]) {
-      const int i = tis[u] * 32 + lr, j = tjs[u] * 32 + lr;
-      if constexpr (BF16) {
-        const __bf16* ka = s.u.b.K1 + i * LDB + 8 * lk;
-        const __bf16* tb = s.u.b.Tt + j * LDB + 8 * lk;
+  int ti0, tj0, ti1, tj1;
+  const bool has0 = kt_tile<D>(w, 0, tri, ti0, tj0);
+  const bool two = has0 && kt_tile<D>(w, 1, tri, ti1, tj1);
+  if (!two) {
+    ti1 = ti0;
+    tj1 = tj0;
+  }
+  // chain a: tile 0 over k in [0, len); chain b: tile 1 over [0, len), or
+  // tile 0 over [len, D)
+  const int len = two ? D : D / 2;
+  const int kb = two ? 0 : D / 2;
+  floatx16 acc0 = {}, acc1 = {};
+  if (has0) {
+    const int ia = ti0 * 32 + lr, ja = tj0 * 32 + lr;
+    const int ib = ti1 * 32 + lr, jb = tj1 * 32 + lr;
+    if constexpr (BF16) {
+      const __bf16* ka = s.u.b.K1 + ia * LDB + 8 * lk;
+      const __bf16* ta = s.u.b.Tt + ja * LDB + 8 * lk;
+      const __bf16* kc = s.u.b.K1 + ib * LDB + 8 * lk + kb;
+      const __bf16* tc = s.u.b.Tt + jb * LDB + 8 * lk + kb;
 #pragma unroll 2
-        for (int k0 = 0; k0 < D; k0 += 16) {
-          const bf16x8 a = *reinterpret_cast<const bf16x8*>(ka + k0);
-          const bf16x8 b = *reinterpret_cast<const bf16x8*>(tb + k0);
-          acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[u], 0, 0, 0);
-        }
-      } else {
-        const int Ri = s.R[i];
-#pragma unroll 4
-        for (int k0 = 0; k0 < D; k0 += 2) {
-          const int k = k0 + lk;
-          acc[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(kentry<D, WEIGHTED>(s, i, k, P, Ri), s.u.f.T[k * LDF + j],
-                                                        acc[u], 0, 0, 0);
-        }
+      for (int k0 = 0; k0 < len; k0 += 16) {
+        const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(ka + k0);
+        const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(ta + k0);
+        const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(kc + k0);
+        const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(tc + k0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc1, 0, 0, 0);
       }
-      mfma_drain();
+    } else {
+      // Operands of step k0 + 2 are read while the matrix cores run step k0.
+      const int Ra = s.R[ia], Rb = s.R[ib];
+      const float* T = s.u.f.T;
+      float a0 = kentry<D, WEIGHTED>(s, ia, lk, P, Ra), b0 = T[lk * LDF + ja];
+      float a1 = kentry<D, WEIGHTED>(s, ib, lk + kb, P, Rb), b1 = T[(lk + kb) * LDF + jb];
+      for (int k0 = 0; k0 < len; k0 += 2) {
+        const int kn = (k0 + 2 < len ? k0 + 2 : 0) + lk;
+        const float na0 = kentry<D, WEIGHTED>(s, ia, kn, P, Ra), nb0 = T[kn * LDF + ja];
+        const float na1 = kentry<D, WEIGHTED>(s, ib, kn + kb, P, Rb), nb1 = T[(kn + kb) * LDF + jb];
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc1, 0, 0, 0);
+        a0 = na0;
+        b0 = nb0;
+        a1 = na1;
+        b1 = nb1;
+      }
+    }
+    mfma_drain();
+    if (!two) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc0[r] += acc1[r];
     }
   }
   __syncthreads();
+  if (has0) {
 #pragma unroll
-  for (int u = 0; u < TPW; ++u) {
-    if (has[u]) {
-      const int j = tjs[u] * 32 + lr;
+    for (int r = 0; r < 16; ++r) Wb[(ti0 * 32 + 8 * (r >> 2) + 4 * lk + (r & 3)) * LDF + tj0 * 32 + lr] = acc0[r];
+    if (two) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) Wb[(tis[u] * 32 + 8 * (r >> 2) + 4 * lk + (r & 3)) * LDF + j] = acc[u][r];
+      for (int r = 0; r < 16; ++r) Wb[(ti1 * 32 + 8 * (r >> 2) + 4 * lk + (r & 3)) * LDF + tj1 * 32 + lr] = acc1[r];
     }
   }
   __syncthreads();
