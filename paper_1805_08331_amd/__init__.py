@@ -134,8 +134,13 @@ class DistResult:
 
 
 def sinkhorn_dist_batch(ctx: Context, hist_a: torch.Tensor, hist_b: torch.Tensor, ia: torch.Tensor,
-                        ib: torch.Tensor, out: DistResult | None = None, ws: torch.Tensor | None = None) -> DistResult:
-    """Algorithm 1 on pairs (hist_a[ia[q]], hist_b[ib[q]])."""
+                        ib: torch.Tensor, out: DistResult | None = None, ws: torch.Tensor | None = None,
+                        check_indices: bool = True) -> DistResult:
+    """Algorithm 1 on pairs (hist_a[ia[q]], hist_b[ib[q]]).
+
+    ``check_indices`` reads the index ranges back to the host (a stream
+    synchronisation); pass False inside graph capture, where the caller
+    guarantees that every index addresses its pool."""
     dev = ctx.device
     for t, nm in ((hist_a, "hist_a"), (hist_b, "hist_b")):
         _need(t, nm, torch.float32, dev)
@@ -146,7 +151,7 @@ def sinkhorn_dist_batch(ctx: Context, hist_a: torch.Tensor, hist_b: torch.Tensor
     n = ia.numel()
     if ib.numel() != n:
         raise ValueError("ia and ib differ in length")
-    if n and (int(ia.min()) < 0 or int(ia.max()) >= hist_a.shape[0]
+    if n and check_indices and (int(ia.min()) < 0 or int(ia.max()) >= hist_a.shape[0]
               or int(ib.min()) < 0 or int(ib.max()) >= hist_b.shape[0]):
         raise IndexError("pair index out of range")
     if out is None:

@@ -278,3 +278,42 @@ def test_kmeans_lloyd_matches_oracle(pds):
     np.testing.assert_allclose(obj, hist_obj, rtol=1e-5)
     for c in range(3):
         np.testing.assert_allclose(zc[c], cents[c], rtol=1e-4, atol=1e-6 * cents[c].max())
+
+
+def test_graph_capture_replays(pds):
+    """The distance launches captured in a HIP graph: every replay, with eager
+    work and synchronisations between replays, equals the eager run bitwise."""
+    d, g, n = 64, 2e-3, 16
+    D1s, D2s = pdgen.pairs_batch(12, n, 5, 2500)
+    with pds.Context(d, g, tol=1e-4, max_iter=3000, precision="bf16") as ctx:
+        pts, off = pdgen.to_csr(list(D1s) + list(D2s))
+        hist, mass, bad = pds.pd_discretize(ctx, torch.from_numpy(pts).cuda(), torch.from_numpy(off).cuda())
+        ia = torch.arange(0, n, dtype=torch.int32, device="cuda")
+        ib = ia + n
+        ref = pds.sinkhorn_dist_batch(ctx, hist, hist, ia, ib)
+        torch.cuda.synchronize()
+        assert int(((hist > 0).sum(dim=(1, 2)) > 512).sum()) > 0    # some pairs take the global-list launch
+        out = pds.DistResult(torch.empty(n, dtype=torch.float64, device="cuda"),
+                             torch.empty((n, 2), dtype=torch.int32, device="cuda"),
+                             torch.empty(n, dtype=torch.float32, device="cuda"),
+                             torch.empty(n, dtype=torch.int32, device="cuda"))
+        ws = ctx.workspace(pds._lib.PDSINK_OP_DIST, n)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            pds.sinkhorn_dist_batch(ctx, hist, hist, ia, ib, out=out, ws=ws, check_indices=False)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            pds.sinkhorn_dist_batch(ctx, hist, hist, ia, ib, out=out, ws=ws, check_indices=False)
+        for _ in range(3):
+            out.cost.fill_(-1.0)
+            out.iters.fill_(-1)
+            out.err.fill_(-1.0)
+            out.status.fill_(-1)
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(out.cost, ref.cost) and torch.equal(out.iters, ref.iters)
+            assert torch.equal(out.err, ref.err) and torch.equal(out.status, ref.status)
