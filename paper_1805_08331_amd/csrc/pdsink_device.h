@@ -91,13 +91,16 @@ __device__ __forceinline__ ESum esum_add(ESum a, ESum b) {
   const int e = max(a.e, b.e);
   return ESum{e, ldxd(a.s, a.e - e) + ldxd(b.s, b.e - e)};
 }
+// Sum over the wave: the largest exponent first, then one scaled sum, so the
+// shuffles carry plain doubles.  (A zero term has exponent NEG and vanishes.)
 __device__ __forceinline__ ESum wave_esum(ESum v) {
+  int e = v.s != 0.0 ? v.e : -(1 << 24);
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    ESum w{__shfl_xor(v.e, o), __shfl_xor(v.s, o)};
-    v = esum_add(v, w);
-  }
-  return v;
+  for (int o = 32; o > 0; o >>= 1) e = max(e, __shfl_xor(e, o));
+  double x = v.s != 0.0 ? ldxd(v.s, v.e - e) : 0.0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return ESum{e, x};
 }
 template <int NW = NWAVE>
 __device__ __forceinline__ ESum block_esum(ESum v, int* rede, double* reds) {

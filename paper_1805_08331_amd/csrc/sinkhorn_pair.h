@@ -242,7 +242,8 @@ __device__ __forceinline__ float kentry(const PairSmem<D>& s, int i, int k, cons
 // from Q and S, 16 consecutive entries of one row per thread and step.  An
 // entry bf16(gm) 2^(P_k + ge - R_i) is assembled directly as a BF16 bit
 // pattern by adding the exponent shift to the table word; results below the
-// smallest normal BF16 (2^-126, at least 2^-166 below the row maximum) are 0.
+// smallest normal BF16 (2^-126, at least 2^-166 below the row maximum) become
+// 0 or a subnormal pattern.
 template <int D>
 __device__ __forceinline__ void build_kernels_bf16(PairSmem<D>& s, const int* P, const int* Q, int d) {
   constexpr int LDB = Cfg<D>::LDB;
@@ -267,10 +268,10 @@ __device__ __forceinline__ void build_kernels_bf16(PairSmem<D>& s, const int* P,
     for (int t = 0; t < 16; t += 2) {
       const int s0 = min(max(xs[t] + base, -(1 << 20)), 1 << 20);
       const int s1 = min(max(xs[t + 1] + base, -(1 << 20)), 1 << 20);
-      int v0 = tw[-t] + (s0 << 7);
-      int v1 = tw[-t - 1] + (s1 << 7);
-      v0 = v0 >= 128 ? v0 : 0;
-      v1 = v1 >= 128 ? v1 : 0;
+      // below the smallest normal the clamp leaves 0 or a BF16 subnormal
+      // pattern (< 2^-126): either is negligible against the row maximum
+      const int v0 = min(max(tw[-t] + (s0 << 7), 0), 0x7FFF);
+      const int v1 = min(max(tw[-t - 1] + (s1 << 7), 0), 0x7FFF);
       pk[t >> 1] = (unsigned)v0 | ((unsigned)v1 << 16);
     }
     uint4* dst = reinterpret_cast<uint4*>((first ? s.u.b.K1 : s.u.b.K2) + i * LDB + k0);
