@@ -1160,8 +1160,9 @@ __device__ __forceinline__ void solve_pair(const PairParams& prm, PairSmem<D>& s
     su.ex = -kv.e;
     su.mx = aD / kv.s;
     ku = esum_add(dotu, ESum{su.ex, su.mx});
-    __syncthreads();
-    // v-update: v = b / K^T u (K is symmetric).
+    // v-update: v = b / K^T u (K is symmetric).  No barrier needed here: the
+    // update ended with one, and the next shared-memory writes (refit
+    // extrema, scales, kernels) touch nothing read after it.
     const int Hu = headroom(su.mres);
     Wb = apply_K<D>(s, s.Pu, s.Qu, d, Hu, lp_now, tri, tri);
     ESum dotv;
@@ -1178,7 +1179,6 @@ __device__ __forceinline__ void solve_pair(const PairParams& prm, PairSmem<D>& s
     ++t;
     if (lp_now) ++it_lp;
     else ++it_hp;
-    __syncthreads();
     if (bad) break;
   }
 
