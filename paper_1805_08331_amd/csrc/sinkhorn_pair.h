@@ -97,6 +97,7 @@ constexpr int MAXSUSP = 256;   // suspects handled per half step
 constexpr int XCHUNK = 4;      // suspects evaluated together
 constexpr int QSUSP = 1 << 28; // per-entry marker: entry is suspect number q - QSUSP
 constexpr int HEAD = 40;       // kernel headroom octaves for an input residual within 2^20
+constexpr int SUSP_MARGIN = 30; // octaves between the dropped-term bound and a trusted value
 
 template <int D>
 struct Cfg {
@@ -778,8 +779,9 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, bool w
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const float mxf = (float)xs.mx;
   // Trusted level of a normalised value: everything the contractions drop is
-  // below 2^(H + mres + 14 - 126) in these units; keep a 2^-40 relative margin.
-  const int thr = H + max(xs.mres, 20) + 14 - 126 + 40;
+  // below 2^(H + mres + 14 - 126) in these units; keep a 2^-SUSP_MARGIN
+  // relative margin (below FP32 rounding of the contraction sums).
+  const int thr = H + max(xs.mres, 20) + 14 - 126 + SUSP_MARGIN;
   // The X buffer can be cleared now (x was consumed by contraction 1) unless
   // an FP32 X overlaps the BF16 K x buffer still being read.
   const bool late_x = !out_bf16 && wb_bf16;
