@@ -510,7 +510,14 @@ struct SupList {
   int q_[SPT];
   int qe_[SPT];
   __device__ __forceinline__ static constexpr int nk() { return SPT; }
-  __device__ __forceinline__ int cell(int k) const { return cell_[k]; }
+  // The cell is opaque to the optimiser at every use, so that addresses derived
+  // from it are recomputed where needed instead of being kept live in
+  // registers across the whole solve.
+  __device__ __forceinline__ int cell(int k) const {
+    int c = cell_[k];
+    asm volatile("" : "+v"(c));
+    return c;
+  }
   __device__ __forceinline__ float tgt(int k) const { return tgt_[k]; }
   __device__ __forceinline__ float res(int k) const { return res_[k]; }
   __device__ __forceinline__ int q(int k) const { return q_[k]; }
