@@ -94,7 +94,6 @@ struct PairParams {
 constexpr int PWGS = 512;      // threads per pair workgroup
 constexpr int PNW = PWGS / 64; // its waves
 constexpr int MAXSUSP = 256;   // suspects handled per half step
-constexpr int XCHUNK = 4;      // suspects evaluated together
 constexpr int QSUSP = 1 << 28; // per-entry marker: entry is suspect number q - QSUSP
 constexpr int HEAD = 40;       // kernel headroom octaves for an input residual within 2^20
 constexpr int SUSP_MARGIN = 30; // octaves between the dropped-term bound and a trusted value
@@ -145,8 +144,8 @@ struct PairSmem {
   int susp_cell[MAXSUSP];
   int susp_e[MAXSUSP];     // value = susp_m * 2^susp_e (natural scale, or absolute for the cost)
   float susp_m[MAXSUSP];
-  int xmax[PNW][XCHUNK];
-  float xsum[PNW][XCHUNK];
+  int xs_cell[PWGS];       // staging of a register support list for the exact path
+  float xs_res[PWGS];
 };
 
 // The K x tile buffer: FP32 [D][LDF], after contraction 2, over storage that
@@ -617,119 +616,83 @@ __device__ __forceinline__ double build_support(PairSmem<D>& s, const float* __r
   return mass;
 }
 
-// Exact values for the suspects [base, base + cnt) from the input x: sum over
-// the support of x of K_(ij),(kl) x_kl (times C_(ij),(kl) when WEIGHTED,
-// Proposition 3) with explicit exponents: pass 1 takes each target's largest
-// term exponent, pass 2 the sum of the terms scaled by it.  x is its support
-// list, or (dense) 1 on every grid cell.  Writes mantissa and absolute log2
-// exponent to out_m / out_e.
+// Exact values for the suspects [0, ns) from the input x: sum over the support
+// of x of K_(ij),(kl) x_kl (times C_(ij),(kl) when WEIGHTED, Proposition 3)
+// with explicit exponents: pass 1 takes the largest term exponent, pass 2 the
+// sum of the terms scaled by it.  One wave per suspect (wave w takes suspects
+// w, w + PNW, ...), its lanes striding over x's entries: no workgroup barrier
+// inside.  x is its support list (register lists are staged to LDS first), or
+// (dense) 1 on every grid cell.  Writes mantissa and absolute log2 exponent to
+// out_m / out_e.
 template <int D, int SPT, bool WEIGHTED>
-__device__ __forceinline__ void exact_chunk(PairSmem<D>& s, const SupList<SPT>& xs, bool dense, int d, const int* Px,
-                                            const int* Qx, int base, int cnt, int* out_e, float* out_m) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  int ti[XCHUNK], tj[XCHUNK], em[XCHUNK];
-#pragma unroll
-  for (int t = 0; t < XCHUNK; ++t) {
-    const int c = t < cnt ? s.susp_cell[base + t] : 0;
-    ti[t] = c / D;
-    tj[t] = c % D;
-    em[t] = QNONE;
+__device__ __forceinline__ void exact_all(PairSmem<D>& s, const SupList<SPT>& xs, bool dense, int d, const int* Px,
+                                          const int* Qx, int ns, int* out_e, float* out_m) {
+  static_assert(SPT <= 1, "register lists of one slot are staged to LDS");
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int* xc;
+  const float* xr;
+  int nx;
+  if constexpr (SPT == 1) {
+    if (!dense) {
+      const int c = xs.cell(0);
+      s.xs_cell[threadIdx.x] = c;
+      s.xs_res[threadIdx.x] = c >= 0 ? xs.res(0) : 0.0f;
+    }
+    __syncthreads();
+    xc = s.xs_cell;
+    xr = s.xs_res;
+    nx = PWGS;
+  } else {
+    xc = xs.cell_;
+    xr = xs.res_;
+    nx = xs.n;
   }
-  const int nd = dense ? (d * d + PWGS - 1) / PWGS : xs.nk();
-  for (int k = 0; k < nd; ++k) {
-    int cell = -1;
-    float x = 0.0f;
-    if (dense) {
-      const int c = tid + PWGS * k;
-      if (c < d * d) {
-        cell = (c / d) * D + (c % d);
+  if (dense) nx = d * d;
+  for (int id = wave; id < ns; id += PNW) {
+    const int c = s.susp_cell[id];
+    const int ti = c / D, tj = c % D;
+    int em = QNONE;
+    for (int e = lane; e < nx; e += 64) {
+      int cell;
+      float x;
+      if (dense) {
+        cell = (e / d) * D + (e % d);
         x = 1.0f;
+      } else {
+        cell = xc[e];
+        x = cell >= 0 ? xr[e] : 0.0f;
       }
-    } else if constexpr (SPT == 0) {
-      cell = xs.cell(k);
-      if (cell >= 0) x = xs.res(k);
-    } else {
-#pragma unroll
-      for (int kk = 0; kk < SPT; ++kk)
-        if (kk == k) {
-          cell = xs.cell(kk);
-          x = xs.res(kk);
-        }
+      if (cell >= 0 && x > 0.0f) {
+        const int kr = cell / D, l = cell % D;
+        em = max(em, Px[kr] + Qx[l] + ilog2f(x) + s.tge[ti - kr + D - 1] + s.tge[tj - l + D - 1]);
+      }
     }
-    if (cell >= 0 && x > 0.0f) {
-      const int kr = cell / D, l = cell % D;
-      const int eb = Px[kr] + Qx[l] + ilog2f(x);
-#pragma unroll
-      for (int t = 0; t < XCHUNK; ++t)
-        em[t] = max(em[t], eb + s.tge[ti[t] - kr + D - 1] + s.tge[tj[t] - l + D - 1]);
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < XCHUNK; ++t) em[t] = wave_max(em[t]);
-  __syncthreads();
-  if (lane == 0) {
-#pragma unroll
-    for (int t = 0; t < XCHUNK; ++t) s.xmax[wave][t] = em[t];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int t = 0; t < XCHUNK; ++t) {
-    int v = s.xmax[0][t];
-    for (int w = 1; w < PNW; ++w) v = max(v, s.xmax[w][t]);
-    em[t] = v;
-  }
-  float acc[XCHUNK];
-#pragma unroll
-  for (int t = 0; t < XCHUNK; ++t) acc[t] = 0.0f;
-  for (int k = 0; k < nd; ++k) {
-    int cell = -1;
-    float x = 0.0f;
-    if (dense) {
-      const int c = tid + PWGS * k;
-      if (c < d * d) {
-        cell = (c / d) * D + (c % d);
+    em = wave_max(em);
+    float acc = 0.0f;
+    for (int e = lane; e < nx; e += 64) {
+      int cell;
+      float x;
+      if (dense) {
+        cell = (e / d) * D + (e % d);
         x = 1.0f;
+      } else {
+        cell = xc[e];
+        x = cell >= 0 ? xr[e] : 0.0f;
       }
-    } else if constexpr (SPT == 0) {
-      cell = xs.cell(k);
-      if (cell >= 0) x = xs.res(k);
-    } else {
-#pragma unroll
-      for (int kk = 0; kk < SPT; ++kk)
-        if (kk == k) {
-          cell = xs.cell(kk);
-          x = xs.res(kk);
-        }
-    }
-    if (cell >= 0 && x > 0.0f) {
-      const int kr = cell / D, l = cell % D;
-      const int eb = Px[kr] + Qx[l];
-#pragma unroll
-      for (int t = 0; t < XCHUNK; ++t) {
-        const int i1 = ti[t] - kr + D - 1, i2 = tj[t] - l + D - 1;
+      if (cell >= 0 && x > 0.0f) {
+        const int kr = cell / D, l = cell % D;
+        const int i1 = ti - kr + D - 1, i2 = tj - l + D - 1;
         float mm = x * s.tgm[i1] * s.tgm[i2];
         if (WEIGHTED) mm *= (s.tc1[i1] + s.tc1[i2]);
-        acc[t] += ldx(mm, eb + s.tge[i1] + s.tge[i2] - em[t]);
+        acc += ldx(mm, Px[kr] + Qx[l] + s.tge[i1] + s.tge[i2] - em);
       }
     }
-  }
-#pragma unroll
-  for (int t = 0; t < XCHUNK; ++t) acc[t] = wave_sum(acc[t]);
-  __syncthreads();
-  if (lane == 0) {
-#pragma unroll
-    for (int t = 0; t < XCHUNK; ++t) s.xsum[wave][t] = acc[t];
-  }
-  __syncthreads();
-  if (tid < cnt) {
-    float v = 0.0f;
-    int e = s.xmax[0][tid];
-    for (int w = 0; w < PNW; ++w) {
-      v += s.xsum[w][tid];
-      e = max(e, s.xmax[w][tid]);
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      out_e[id] = em;
+      out_m[id] = acc;
     }
-    out_e[tid] = e;
-    out_m[tid] = v;
   }
   __syncthreads();
 }
@@ -874,9 +837,7 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, bool w
 
   // Suspects: exact values, then their row extrema and error terms.
   if (ns > 0) {
-    for (int base = 0; base < ns; base += XCHUNK)
-      exact_chunk<D, SPT, false>(s, xsup, x_dense, d, Px, Qx, base, min(XCHUNK, ns - base), s.susp_e + base,
-                                 s.susp_m + base);
+    exact_all<D, SPT, false>(s, xsup, x_dense, d, Px, Qx, ns, s.susp_e, s.susp_m);
     for (int id = tid; id < ns; id += PWGS) {
       const int c = s.susp_cell[id], i = c / D, j = c % D;
       const int dl = j - i + D - 1;
@@ -1232,9 +1193,7 @@ __device__ __forceinline__ void solve_pair(const PairParams& prm, PairSmem<D>& s
   }
   const int ns = bad ? 0 : min(s.nsusp, MAXSUSP);
   if (ns > 0) {
-    for (int base = 0; base < ns; base += XCHUNK)
-      exact_chunk<D, SPT, true>(s, vb, v_dense, d, s.Pv, s.Qv, base, min(XCHUNK, ns - base), s.susp_e + base,
-                                s.susp_m + base);
+    exact_all<D, SPT, true>(s, vb, v_dense, d, s.Pv, s.Qv, ns, s.susp_e, s.susp_m);
 #pragma unroll
     for (int k = 0; k < nka; ++k) {
       const int qk = ua.q(k);
