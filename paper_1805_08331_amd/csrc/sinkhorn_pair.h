@@ -621,25 +621,47 @@ __device__ __forceinline__ double build_support(PairSmem<D>& s, const float* __r
 // with explicit exponents: pass 1 takes the largest term exponent, pass 2 the
 // sum of the terms scaled by it.  One wave per suspect (wave w takes suspects
 // w, w + PNW, ...), its lanes striding over x's entries: no workgroup barrier
-// inside.  x is its support list (register lists are staged to LDS first), or
-// (dense) 1 on every grid cell.  Writes mantissa and absolute log2 exponent to
-// out_m / out_e.
-template <int D, int SPT, bool WEIGHTED>
+// inside.  x is its support list (register lists are staged to LDS first,
+// unless `staged`), or (dense) 1 on every grid cell.  Writes mantissa and
+// absolute log2 exponent to out_m / out_e; with FIN, instead the value in the
+// natural scale of cell (i, j), 2^-(R_i + S_j), plus the diagonal-bin term
+// x_Delta k_Delta,ij of the K application (xD_e, xD_m: x_Delta), flagging
+// s.sflag when the total vanishes.
+template <int D, int SPT, bool WEIGHTED, bool FIN>
 __device__ __forceinline__ void exact_all(PairSmem<D>& s, const SupList<SPT>& xs, bool dense, int d, const int* Px,
-                                          const int* Qx, int ns, int* out_e, float* out_m) {
+                                          const int* Qx, int ns, int* out_e, float* out_m, bool staged = false,
+                                          int xD_e = 0, float xD_m = 0.0f) {
   static_assert(SPT <= 1, "register lists of one slot are staged to LDS");
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int* xc;
   const float* xr;
   int nx;
+  auto finish = [&](int id, int c, int em, float acc) {
+    if constexpr (FIN) {
+      const int i = c / D, j = c % D, dl = j - i + D - 1;
+      const ESum g{em - s.R[i] - s.S[j], (double)acc};
+      const ESum tot = esum_add(g, ESum{xD_e + s.tgde[dl] - s.R[i] - s.S[j], (double)(xD_m * s.tgdm[dl])});
+      if (tot.s > 0.0) {
+        out_e[id] = tot.e;
+        out_m[id] = (float)tot.s;
+      } else {
+        atomicOr(&s.sflag, 1);
+        out_e[id] = 0;
+        out_m[id] = 1.0f;
+      }
+    } else {
+      out_e[id] = em;
+      out_m[id] = acc;
+    }
+  };
   if constexpr (SPT == 1) {
-    if (!dense) {
+    if (!dense && !staged) {
       const int c = xs.cell(0);
       s.xs_cell[threadIdx.x] = c;
       s.xs_res[threadIdx.x] = c >= 0 ? xs.res(0) : 0.0f;
     }
-    __syncthreads();
+    if (!staged) __syncthreads();
     xc = s.xs_cell;
     xr = s.xs_res;
     nx = PWGS;
@@ -649,6 +671,48 @@ __device__ __forceinline__ void exact_all(PairSmem<D>& s, const SupList<SPT>& xs
     nx = xs.n;
   }
   if (dense) nx = d * d;
+  if constexpr (SPT == 1) {
+    if (!dense) {
+      // PWGS / 64 staged entries per lane, kept in registers for both passes
+      constexpr int EPL = PWGS / 64;
+      int kr[EPL], l[EPL], eb[EPL];
+      float xm[EPL];
+#pragma unroll
+      for (int u = 0; u < EPL; ++u) {
+        const int cell = xc[lane + 64 * u];
+        const float x = xr[lane + 64 * u];
+        const bool ok = cell >= 0 && x > 0.0f;
+        kr[u] = ok ? cell / D : 0;
+        l[u] = ok ? cell % D : 0;
+        xm[u] = ok ? x : 0.0f;
+        eb[u] = ok ? Px[kr[u]] + Qx[l[u]] : QNONE;
+      }
+      for (int id = wave; id < ns; id += PNW) {
+        const int c = s.susp_cell[id];
+        const int ti = c / D, tj = c % D;
+        int em = QNONE;
+#pragma unroll
+        for (int u = 0; u < EPL; ++u)
+          if (eb[u] != QNONE)
+            em = max(em, eb[u] + ilog2f(xm[u]) + s.tge[ti - kr[u] + D - 1] + s.tge[tj - l[u] + D - 1]);
+        em = wave_max(em);
+        float acc = 0.0f;
+#pragma unroll
+        for (int u = 0; u < EPL; ++u) {
+          if (eb[u] != QNONE) {
+            const int i1 = ti - kr[u] + D - 1, i2 = tj - l[u] + D - 1;
+            float mm = xm[u] * s.tgm[i1] * s.tgm[i2];
+            if (WEIGHTED) mm *= (s.tc1[i1] + s.tc1[i2]);
+            acc += ldx(mm, eb[u] + s.tge[i1] + s.tge[i2] - em);
+          }
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) finish(id, c, em, acc);
+      }
+      __syncthreads();
+      return;
+    }
+  }
   for (int id = wave; id < ns; id += PNW) {
     const int c = s.susp_cell[id];
     const int ti = c / D, tj = c % D;
@@ -689,10 +753,7 @@ __device__ __forceinline__ void exact_all(PairSmem<D>& s, const SupList<SPT>& xs
       }
     }
     acc = wave_sum(acc);
-    if (lane == 0) {
-      out_e[id] = em;
-      out_m[id] = acc;
-    }
+    if (lane == 0) finish(id, c, em, acc);
   }
   __syncthreads();
 }
@@ -805,6 +866,13 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, bool w
       }
     }
   }
+  if constexpr (SPT == 1) {   // x's list, for the exact path should a cell be suspect
+    if (!x_dense) {
+      const int c = xsup.cell(0);
+      s.xs_cell[tid] = c;
+      s.xs_res[tid] = c >= 0 ? xsup.res(0) : 0.0f;
+    }
+  }
   if (!late_x) {
     if (clear_all) {
       zero_x<D>(s, out_bf16);
@@ -837,22 +905,7 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, bool w
 
   // Suspects: exact values, then their row extrema and error terms.
   if (ns > 0) {
-    exact_all<D, SPT, false>(s, xsup, x_dense, d, Px, Qx, ns, s.susp_e, s.susp_m);
-    for (int id = tid; id < ns; id += PWGS) {
-      const int c = s.susp_cell[id], i = c / D, j = c % D;
-      const int dl = j - i + D - 1;
-      const ESum g{s.susp_e[id] - s.R[i] - s.S[j], (double)s.susp_m[id]};
-      const ESum tot = esum_add(g, ESum{xs.ex + s.tgde[dl] - s.R[i] - s.S[j], (double)(mxf * s.tgdm[dl])});
-      if (tot.s > 0.0) {
-        s.susp_e[id] = tot.e;
-        s.susp_m[id] = (float)tot.s;
-      } else {
-        atomicOr(&s.sflag, 1);
-        s.susp_e[id] = 0;
-        s.susp_m[id] = 1.0f;
-      }
-    }
-    __syncthreads();
+    exact_all<D, SPT, false, true>(s, xsup, x_dense, d, Px, Qx, ns, s.susp_e, s.susp_m, true, xs.ex, mxf);
     double eg2 = 0.0;
 #pragma unroll
     for (int k = 0; k < nk; ++k) {
@@ -1193,7 +1246,7 @@ __device__ __forceinline__ void solve_pair(const PairParams& prm, PairSmem<D>& s
   }
   const int ns = bad ? 0 : min(s.nsusp, MAXSUSP);
   if (ns > 0) {
-    exact_all<D, SPT, true>(s, vb, v_dense, d, s.Pv, s.Qv, ns, s.susp_e, s.susp_m);
+    exact_all<D, SPT, true, false>(s, vb, v_dense, d, s.Pv, s.Qv, ns, s.susp_e, s.susp_m);
 #pragma unroll
     for (int k = 0; k < nka; ++k) {
       const int qk = ua.q(k);
