@@ -55,9 +55,9 @@ extern "C" {
 typedef struct pdsink_ctx pdsink_ctx;
 
 typedef struct {
-  int32_t d;            /* grid size, 2 <= d <= 128                                    */
+  int32_t d;            /* grid size, 2 <= d <= 256                                    */
   double  p;            /* ground exponent, p >= 1 (the paper's experiments use 2)     */
-  double  gamma;        /* entropic parameter, > 0, in cost units of [0,1]^2           */
+  double  gamma;        /* entropic parameter, >= 1e-5, in cost units of [0,1]^2       */
   double  tol;          /* stop when (||P1-a||_1 + |.|_Delta)/m <= tol; 0 = run max_iter */
   int32_t max_iter;     /* cap on full (u, v) iterations, >= 1                         */
   int32_t precision;    /* PDSINK_FP32 or PDSINK_BF16_REFINE                           */
@@ -69,8 +69,10 @@ typedef struct {
  * parameters and uploads the per-(d, gamma, p) tables of the 1-D kernels
  * k = exp(-c/gamma), k_Delta and costs c, c_Delta (section 3, the tables
  * before Propositions 2 and 3), as exact (exponent, mantissa) pairs.
- * (host) params, (host) out.  Returns PDSINK_EINVAL for d outside [2, 128],
- * p < 1, gamma <= 0, tol < 0, max_iter < 1 or an unknown precision. */
+ * (host) params, (host) out.  Returns PDSINK_EINVAL for d outside [2, 256],
+ * p < 1, gamma < 1e-5 (the integer log2 scales of the iterates, about
+ * 1.44 / gamma octaves, must stay far inside the int32 range the kernels
+ * use), tol < 0, max_iter < 1 or an unknown precision. */
 int pdsink_ctx_create(const pdsink_params* params, int device, pdsink_ctx** out);
 
 /* Release the context's device tables.  NULL is a no-op. */

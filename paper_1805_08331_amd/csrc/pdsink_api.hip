@@ -21,7 +21,7 @@ using namespace pdsink;
 struct pdsink_ctx {
   pdsink_params prm;
   int device;
-  int D;              // padded grid: 32, 64 or 128
+  int D;              // padded grid: 32, 64, 128 or 256
   int* ge;            // device tables, 2*D - 1 entries each
   float* gm;
   int* gde;
@@ -34,7 +34,7 @@ struct pdsink_ctx {
 
 namespace {
 
-int pad_grid(int d) { return d <= 32 ? 32 : (d <= 64 ? 64 : 128); }
+int pad_grid(int d) { return d <= 32 ? 32 : (d <= 64 ? 64 : (d <= 128 ? 128 : 256)); }
 
 struct DeviceGuard {
   int old = -1;
@@ -73,12 +73,18 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int last_error() { return hipGetLastError() == hipSuccess ? PDSINK_OK : PDSINK_EDEVICE; }
 
+// One workgroup per diagram.  The counts go to an LDS histogram (GLOBAL_H:
+// straight to the output, zeroed first, for grids whose histogram exceeds
+// 64 KB); float atomic adds of whole counts below 2^24 are exact, so the
+// result does not depend on their order.
+template <bool GLOBAL_H>
 __global__ __launch_bounds__(WG) void discretize_kernel(const float* __restrict__ pts, const int64_t* __restrict__ off,
                                                         int d, float* __restrict__ hist, double* __restrict__ mass,
                                                         int* __restrict__ n_bad) {
-  extern __shared__ float h[];
+  extern __shared__ float hs[];
   __shared__ double red[NWAVE];
   const int64_t n = blockIdx.x;
+  float* h = GLOBAL_H ? hist + n * d * d : hs;
   for (int c = threadIdx.x; c < d * d; c += WG) h[c] = 0.0f;
   __syncthreads();
   const int64_t p0 = off[n], p1 = off[n + 1];
@@ -102,14 +108,17 @@ __global__ __launch_bounds__(WG) void discretize_kernel(const float* __restrict_
     bad = wave_sum(bad);
     if ((threadIdx.x & 63) == 0 && bad) atomicAdd(n_bad, bad);
   }
-  __syncthreads();
-  for (int c = threadIdx.x; c < d * d; c += WG) hist[n * d * d + c] = h[c];
+  if (!GLOBAL_H) {
+    __syncthreads();
+    for (int c = threadIdx.x; c < d * d; c += WG) hist[n * d * d + c] = h[c];
+  }
   if (threadIdx.x == 0) mass[n] = kept;
 }
 
 // Optional per-pair buffers of a distance launch.
 struct PairExtras {
   char* lists = nullptr;      // global support lists, list_bytes(D) per workgroup slot
+  char* ops = nullptr;        // operand slices (D = 256), GlobalOps<256>::BYTES per slot
   int n_slots = 0;            // workgroup slots (grid of the global-list variant)
   char* state = nullptr;      // WarmState per pair
   int state_in = 0;
@@ -121,9 +130,13 @@ size_t warm_bytes(int D) {
   switch (D) {
     case 32: return sizeof(WarmState<32>);
     case 64: return sizeof(WarmState<64>);
-    default: return sizeof(WarmState<128>);
+    case 128: return sizeof(WarmState<128>);
+    default: return sizeof(WarmState<256>);
   }
 }
+size_t ops_bytes(int D) { return D > 128 ? GlobalOps<256>::BYTES : 0; }
+// Per workgroup slot of a launch: support lists, plus operand buffers beyond D = 128.
+size_t slot_bytes(int D) { return list_bytes(D) + ops_bytes(D); }
 int64_t slots_for(const pdsink_ctx* ctx, int64_t n_pairs) { return n_pairs < ctx->n_cu ? n_pairs : ctx->n_cu; }
 
 // Level 0 runs every pair with one support entry per thread and register
@@ -135,7 +148,9 @@ int64_t slots_for(const pdsink_ctx* ctx, int64_t n_pairs) { return n_pairs < ctx
 template <int D>
 int launch_levels(PairParams pp, int n_slots, hipStream_t st) {
   pp.only_redo = 0;
-  hipLaunchKernelGGL((sinkhorn_pair_kernel<D, 1>), dim3((unsigned)pp.n_pairs), dim3(PWGS), 0, st, pp);
+  // beyond D = 128 every launch strides over the batch with one operand slice per slot
+  const unsigned g0 = D > 128 ? (unsigned)n_slots : (unsigned)pp.n_pairs;
+  hipLaunchKernelGGL((sinkhorn_pair_kernel<D, 1>), dim3(g0), dim3(PWGS), 0, st, pp);
   int rc = last_error();
   if (rc) return rc;
   pp.only_redo = 1;
@@ -171,13 +186,15 @@ int run_pairs(const pdsink_ctx* ctx, int64_t n_pairs, const float* ha, const flo
   pp.redo = redo;
   pp.lists = ex.lists;
   pp.list_stride = list_bytes(ctx->D);
+  pp.ops = ex.ops;
   pp.state = ex.state;
   pp.state_in = ex.state_in;
   pp.gout = ex.gout;
   switch (ctx->D) {
     case 32: return launch_levels<32>(pp, ex.n_slots, st);
     case 64: return launch_levels<64>(pp, ex.n_slots, st);
-    default: return launch_levels<128>(pp, ex.n_slots, st);
+    case 128: return launch_levels<128>(pp, ex.n_slots, st);
+    default: return launch_levels<256>(pp, ex.n_slots, st);
   }
 }
 
@@ -277,9 +294,9 @@ int pdsink_ctx_create(const pdsink_params* params, int device, pdsink_ctx** out)
   if (!params || !out) return PDSINK_EINVAL;
   *out = nullptr;
   const pdsink_params& p = *params;
-  if (p.d < 2 || p.d > 128 || !(p.p >= 1.0) || !(p.gamma > 0.0) || !(p.tol >= 0.0) || p.max_iter < 1 ||
+  if (p.d < 2 || p.d > 256 || !(p.p >= 1.0) || !(p.gamma > 0.0) || !(p.tol >= 0.0) || p.max_iter < 1 ||
       (p.precision != PDSINK_FP32 && p.precision != PDSINK_BF16_REFINE) || !(p.switch_tol >= 0.0) ||
-      !std::isfinite(p.gamma) || !std::isfinite(p.p))
+      !std::isfinite(p.gamma) || !std::isfinite(p.p) || p.gamma < 1e-5)
     return PDSINK_EINVAL;
   DeviceGuard g(device);
   if (!g.ok) return PDSINK_EDEVICE;
@@ -363,15 +380,15 @@ int pdsink_workspace_bytes(const pdsink_ctx* ctx, int op, int64_t n_items, size_
   if (!ctx || !bytes || n_items < 0) return PDSINK_EINVAL;
   switch (op) {
     case PDSINK_OP_DIST:   // routing flag per pair, support lists per slot
-      *bytes = align256(n_items) + slots_for(ctx, n_items) * list_bytes(ctx->D);
+      *bytes = align256(n_items) + slots_for(ctx, n_items) * slot_bytes(ctx->D);
       return PDSINK_OK;
     case PDSINK_OP_KMEANS:   // ia, ib, cost, iters, err, status, redo per pair, lists per slot
       *bytes = align256(n_items * 4) * 2 + align256(n_items * 8) + align256(n_items * 8) + align256(n_items * 4) * 2 +
-               align256(n_items) + slots_for(ctx, n_items) * list_bytes(ctx->D);
+               align256(n_items) + slots_for(ctx, n_items) * slot_bytes(ctx->D);
       return PDSINK_OK;
     case PDSINK_OP_BARYCENTER:   // the KMEANS arrays for n pairs, warm states, gradient terms
       *bytes = align256(n_items * 4) * 2 + align256(n_items * 8) + align256(n_items * 8) + align256(n_items * 4) * 2 +
-               align256(n_items) + slots_for(ctx, n_items) * list_bytes(ctx->D) +
+               align256(n_items) + slots_for(ctx, n_items) * slot_bytes(ctx->D) +
                align256(n_items * warm_bytes(ctx->D)) + align256(n_items * 8 * (size_t)ctx->prm.d * ctx->prm.d);
       return PDSINK_OK;
     default: return PDSINK_EINVAL;
@@ -386,8 +403,12 @@ int pd_discretize(pdsink_ctx* ctx, const float* pts, const int64_t* offsets, int
   DeviceGuard g(ctx->device);
   if (!g.ok) return PDSINK_EDEVICE;
   const int d = ctx->prm.d;
-  hipLaunchKernelGGL(discretize_kernel, dim3((unsigned)n_diag), dim3(WG), (size_t)d * d * sizeof(float),
-                     (hipStream_t)stream, pts, offsets, d, hist, mass, n_bad);
+  if ((size_t)d * d * sizeof(float) <= 65536)
+    hipLaunchKernelGGL(discretize_kernel<false>, dim3((unsigned)n_diag), dim3(WG), (size_t)d * d * sizeof(float),
+                       (hipStream_t)stream, pts, offsets, d, hist, mass, n_bad);
+  else
+    hipLaunchKernelGGL(discretize_kernel<true>, dim3((unsigned)n_diag), dim3(WG), 0, (hipStream_t)stream, pts, offsets,
+                       d, hist, mass, n_bad);
   return last_error();
 }
 
@@ -404,8 +425,9 @@ int sinkhorn_dist_batch(pdsink_ctx* ctx, int64_t n_pairs, const float* hist_a, c
   DeviceGuard g(ctx->device);
   if (!g.ok) return PDSINK_EDEVICE;
   PairExtras ex;
-  ex.lists = (char*)ws + align256(n_pairs);
   ex.n_slots = (int)slots_for(ctx, n_pairs);
+  ex.lists = (char*)ws + align256(n_pairs);
+  ex.ops = ex.lists + ex.n_slots * list_bytes(ctx->D);
   return run_pairs(ctx, n_pairs, hist_a, hist_b, ia, ib, cost, iters, err, status, (unsigned char*)ws, ex,
                    (hipStream_t)stream);
 }
@@ -440,6 +462,7 @@ int kmeans_assign(pdsink_ctx* ctx, int64_t n_diag, const float* hist, int32_t k,
   PairExtras ex;
   ex.lists = w;
   ex.n_slots = (int)slots_for(ctx, np);
+  ex.ops = w + ex.n_slots * list_bytes(ctx->D);
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(kmeans_pairs_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, n_diag, k, ia, ib);
   int rc = last_error();
@@ -482,7 +505,8 @@ int pd_barycenter(pdsink_ctx* ctx, int64_t n_diag, const float* hist, double lam
   PairExtras ex;
   ex.lists = w;
   ex.n_slots = (int)slots_for(ctx, N);
-  w += ex.n_slots * list_bytes(ctx->D);
+  ex.ops = w + ex.n_slots * list_bytes(ctx->D);
+  w += ex.n_slots * slot_bytes(ctx->D);
   ex.state = w;
   w += align256(N * warm_bytes(ctx->D));
   ex.gout = (double*)w;

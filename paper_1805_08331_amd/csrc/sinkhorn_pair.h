@@ -82,6 +82,8 @@ struct PairParams {
   // support lists of the global-list variant: list_stride bytes per workgroup
   char* lists;
   size_t list_stride;
+  // operand slices (grids beyond 128): GlobalOps<D>::BYTES per workgroup
+  char* ops;
   // optional warm start of v (WarmState per pair): read when state_in, and
   // written with the final v
   char* state;
@@ -107,8 +109,11 @@ struct Cfg {
   static constexpr int TPR = PWGS / (2 * D); // threads per (side, row) in compute_RS
 };
 
-template <int D>
-struct PairSmem {
+// Operand buffers of the contractions and the support-list staging area:
+// in LDS for D <= 128; for larger grids they live in a per-workgroup slice of
+// the workspace (GlobalOps) and the LDS part is empty.
+template <int D, bool G = (D > 128)>
+struct OpsLds {
   using C = Cfg<D>;
   union {
     struct {
@@ -126,6 +131,23 @@ struct PairSmem {
       float val[D * D];
     } st;
   } u;
+};
+template <int D>
+struct OpsLds<D, true> {};
+
+// Layout of the global operand slice (grids beyond 128): the same buffers as
+// the LDS union, plus a K x buffer of its own.
+template <int D>
+struct GlobalOps {
+  using C = Cfg<D>;
+  static constexpr size_t F = (size_t)2 * D * C::LDF * 4, B = (size_t)4 * D * C::LDB * 2, S = (size_t)2 * D * D * 4;
+  static constexpr size_t UNION = ((F > B ? (F > S ? F : S) : (B > S ? B : S)) + 255) & ~(size_t)255;
+  static constexpr size_t W = UNION;                                   // K x buffer, FP32 [D][LDF]
+  static constexpr size_t BYTES = (W + (size_t)D * C::LDF * 4 + 255) & ~(size_t)255;
+};
+
+template <int D>
+struct PairSmem : OpsLds<D> {
   int tge[2 * D], tgde[2 * D], tkb[2 * D];
   float tgm[2 * D], tgdm[2 * D], tc1[2 * D], tcd[2 * D];
   alignas(16) int Pu[D];
@@ -146,13 +168,58 @@ struct PairSmem {
   float susp_m[MAXSUSP];
   int xs_cell[PWGS];       // staging of a register support list for the exact path
   float xs_res[PWGS];
+  char* gops;              // global operand slice (grids beyond 128)
 };
 
-// The K x tile buffer: FP32 [D][LDF], after contraction 2, over storage that
-// is dead by then (T in FP32 mode; Tt and K1 in BF16 mode).
+// Operand buffers (LDS union, or the global slice beyond D = 128).
+template <int D>
+__device__ __forceinline__ float* opXf(PairSmem<D>& s) {
+  if constexpr (D <= 128) return s.u.f.X;
+  else return reinterpret_cast<float*>(s.gops);
+}
+template <int D>
+__device__ __forceinline__ float* opTf(PairSmem<D>& s) {
+  if constexpr (D <= 128) return s.u.f.T;
+  else return reinterpret_cast<float*>(s.gops) + D * Cfg<D>::LDF;
+}
+template <int D>
+__device__ __forceinline__ __bf16* opXb(PairSmem<D>& s) {
+  if constexpr (D <= 128) return s.u.b.X;
+  else return reinterpret_cast<__bf16*>(s.gops);
+}
+template <int D>
+__device__ __forceinline__ __bf16* opTtb(PairSmem<D>& s) {
+  if constexpr (D <= 128) return s.u.b.Tt;
+  else return reinterpret_cast<__bf16*>(s.gops) + D * Cfg<D>::LDB;
+}
+template <int D>
+__device__ __forceinline__ __bf16* opK1b(PairSmem<D>& s) {
+  if constexpr (D <= 128) return s.u.b.K1;
+  else return reinterpret_cast<__bf16*>(s.gops) + 2 * D * Cfg<D>::LDB;
+}
+template <int D>
+__device__ __forceinline__ __bf16* opK2b(PairSmem<D>& s) {
+  if constexpr (D <= 128) return s.u.b.K2;
+  else return reinterpret_cast<__bf16*>(s.gops) + 3 * D * Cfg<D>::LDB;
+}
+template <int D>
+__device__ __forceinline__ int* stCell(PairSmem<D>& s) {
+  if constexpr (D <= 128) return s.u.st.cell;
+  else return reinterpret_cast<int*>(s.gops);
+}
+template <int D>
+__device__ __forceinline__ float* stVal(PairSmem<D>& s) {
+  if constexpr (D <= 128) return s.u.st.val;
+  else return reinterpret_cast<float*>(s.gops) + D * D;
+}
+
+// The K x tile buffer: FP32 [D][LDF], after contraction 2.  In LDS it lies
+// over storage that is dead by then (T in FP32 mode; Tt and K1 in BF16
+// mode); beyond D = 128 it has its own place in the global slice.
 template <int D>
 __device__ __forceinline__ float* wbuf(PairSmem<D>& s, bool bf16) {
-  return bf16 ? reinterpret_cast<float*>(s.u.b.Tt) : s.u.f.T;
+  if constexpr (D <= 128) return bf16 ? reinterpret_cast<float*>(s.u.b.Tt) : s.u.f.T;
+  else return reinterpret_cast<float*>(s.gops + GlobalOps<D>::W);
 }
 
 // Kernel headroom for an input whose residual spans +-mres octaves.
@@ -274,7 +341,7 @@ __device__ __forceinline__ void build_kernels_bf16(PairSmem<D>& s, const int* P,
       const int v1 = min(max(tw[-t - 1] + (s1 << 7), 0), 0x7FFF);
       pk[t >> 1] = (unsigned)v0 | ((unsigned)v1 << 16);
     }
-    uint4* dst = reinterpret_cast<uint4*>((first ? s.u.b.K1 : s.u.b.K2) + i * LDB + k0);
+    uint4* dst = reinterpret_cast<uint4*>((first ? opK1b<D>(s) : opK2b<D>(s)) + i * LDB + k0);
     dst[0] = uint4{pk[0], pk[1], pk[2], pk[3]};
     dst[1] = uint4{pk[4], pk[5], pk[6], pk[7]};
   }
@@ -283,7 +350,7 @@ __device__ __forceinline__ void build_kernels_bf16(PairSmem<D>& s, const int* P,
     const int i = item % d, sc = item / d;
     const bool first = sc < nz;
     const int k0 = 16 * (nch + (first ? sc : sc - nz));
-    uint4* dst = reinterpret_cast<uint4*>((first ? s.u.b.K1 : s.u.b.K2) + i * LDB + k0);
+    uint4* dst = reinterpret_cast<uint4*>((first ? opK1b<D>(s) : opK2b<D>(s)) + i * LDB + k0);
     dst[0] = uint4{0u, 0u, 0u, 0u};
     dst[1] = uint4{0u, 0u, 0u, 0u};
   }
@@ -454,6 +521,97 @@ __device__ __forceinline__ void gemm_kt(PairSmem<D>& s, const int* P, float* Wb,
   __syncthreads();
 }
 
+// The contractions for grids beyond 128 (operands in the global slice): one
+// tile at a time per wave, tiles w, w + 8, ...; the K x buffer has its own
+// storage, so each tile is stored as soon as it is done.
+template <int D, bool BF16, bool WEIGHTED>
+__device__ __forceinline__ void gemm_xk_g(PairSmem<D>& s, const int* Q, bool trim) {
+  constexpr int NT = Cfg<D>::NT, LDF = Cfg<D>::LDF, LDB = Cfg<D>::LDB;
+  const int lane = threadIdx.x & 63, lr = lane & 31, lk = lane >> 5;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int tile = w; tile < NT * NT; tile += PNW) {
+    const int tk = tile / NT, tj = tile % NT;
+    const int row = tk * 32 + lr, j = tj * 32 + lr;
+    const int lbeg = trim ? tk * 32 : 0;
+    floatx16 acc = {};
+    if constexpr (BF16) {
+      const __bf16* xa = opXb<D>(s) + row * LDB + 8 * lk;
+      const __bf16* kb = opK2b<D>(s) + j * LDB + 8 * lk;
+#pragma unroll 2
+      for (int l0 = lbeg; l0 < D; l0 += 16) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(xa + l0);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(kb + l0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+      }
+      mfma_drain();
+      __bf16* tt = opTtb<D>(s);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) tt[j * LDB + tk * 32 + 8 * (r >> 2) + 4 * lk + (r & 3)] = (__bf16)acc[r];
+    } else {
+      const int Sj = s.S[j];
+      const float* X = opXf<D>(s);
+#pragma unroll 4
+      for (int l0 = lbeg; l0 < D; l0 += 2) {
+        const int l = l0 + lk;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(X[row * LDF + l], kentry<D, WEIGHTED>(s, j, l, Q, Sj), acc, 0, 0,
+                                                   0);
+      }
+      mfma_drain();
+      float* T = opTf<D>(s);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) T[(tk * 32 + 8 * (r >> 2) + 4 * lk + (r & 3)) * LDF + j] = acc[r];
+    }
+  }
+}
+
+template <int D, bool BF16, bool WEIGHTED>
+__device__ __forceinline__ void gemm_kt_g(PairSmem<D>& s, const int* P, float* Wb, bool tri) {
+  constexpr int LDF = Cfg<D>::LDF, LDB = Cfg<D>::LDB;
+  const int lane = threadIdx.x & 63, lr = lane & 31, lk = lane >> 5;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int ti, tj;
+  for (int u = 0; kt_tile<D>(w, u, tri, ti, tj); ++u) {
+    const int i = ti * 32 + lr, j = tj * 32 + lr;
+    floatx16 acc = {};
+    if constexpr (BF16) {
+      const __bf16* ka = opK1b<D>(s) + i * LDB + 8 * lk;
+      const __bf16* tb = opTtb<D>(s) + j * LDB + 8 * lk;
+#pragma unroll 2
+      for (int k0 = 0; k0 < D; k0 += 16) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(ka + k0);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(tb + k0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+      }
+    } else {
+      const int Ri = s.R[i];
+      const float* T = opTf<D>(s);
+#pragma unroll 4
+      for (int k0 = 0; k0 < D; k0 += 2) {
+        const int k = k0 + lk;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(kentry<D, WEIGHTED>(s, i, k, P, Ri), T[k * LDF + j], acc, 0, 0, 0);
+      }
+    }
+    mfma_drain();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) Wb[(ti * 32 + 8 * (r >> 2) + 4 * lk + (r & 3)) * LDF + j] = acc[r];
+  }
+  __syncthreads();
+}
+
+// Contractions of one K application (LDS or global operands).
+template <int D, bool BF16, bool WEIGHTED1, bool WEIGHTED2>
+__device__ __forceinline__ void contract(PairSmem<D>& s, const int* P, const int* Q, float* Wb, bool trim, bool tri) {
+  if constexpr (D <= 128) {
+    gemm_xk<D, BF16, WEIGHTED1>(s, Q, trim);
+    __syncthreads();
+    gemm_kt<D, BF16, WEIGHTED2>(s, P, Wb, tri);
+  } else {
+    gemm_xk_g<D, BF16, WEIGHTED1>(s, Q, trim);
+    __syncthreads();
+    gemm_kt_g<D, BF16, WEIGHTED2>(s, P, Wb, tri);
+  }
+}
+
 // (K x) on the grid for input scales P, Q (residual already in the X buffer of
 // the matching format) into the K x buffer, scaled by 2^-(R_i + S_j).  `trim`:
 // x vanishes below the diagonal; `tri`: only cells on or above it are read.
@@ -467,13 +625,9 @@ __device__ __forceinline__ float* apply_K(PairSmem<D>& s, const int* P, const in
   if (lowp) {
     build_kernels_bf16<D>(s, P, Q, d);
     __syncthreads();
-    gemm_xk<D, true, false>(s, Q, trim);
-    __syncthreads();
-    gemm_kt<D, true, false>(s, P, Wb, tri);
+    contract<D, true, false, false>(s, P, Q, Wb, trim, tri);
   } else {
-    gemm_xk<D, false, false>(s, Q, trim);
-    __syncthreads();
-    gemm_kt<D, false, false>(s, P, Wb, tri);
+    contract<D, false, false, false>(s, P, Q, Wb, trim, tri);
   }
   return Wb;
 }
@@ -482,17 +636,17 @@ __device__ __forceinline__ float* apply_K(PairSmem<D>& s, const int* P, const in
 template <int D>
 __device__ __forceinline__ void zero_x(PairSmem<D>& s, bool bf16) {
   if (bf16) {
-    for (int c = threadIdx.x; c < D * Cfg<D>::LDB / 8; c += PWGS) reinterpret_cast<bf16x8*>(s.u.b.X)[c] = bf16x8{};
+    for (int c = threadIdx.x; c < D * Cfg<D>::LDB / 8; c += PWGS) reinterpret_cast<bf16x8*>(opXb<D>(s))[c] = bf16x8{};
   } else {
-    for (int c = threadIdx.x; c < D * Cfg<D>::LDF; c += PWGS) s.u.f.X[c] = 0.0f;
+    for (int c = threadIdx.x; c < D * Cfg<D>::LDF; c += PWGS) opXf<D>(s)[c] = 0.0f;
   }
 }
 
 template <int D>
 __device__ __forceinline__ void put_x(PairSmem<D>& s, int cell, float v, bool bf16) {
   const int i = cell / D, j = cell % D;
-  if (bf16) s.u.b.X[i * Cfg<D>::LDB + j] = (__bf16)v;
-  else s.u.f.X[i * Cfg<D>::LDF + j] = v;
+  if (bf16) opXb<D>(s)[i * Cfg<D>::LDB + j] = (__bf16)v;
+  else opXf<D>(s)[i * Cfg<D>::LDF + j] = v;
 }
 
 // One side's support list (u on supp(a) or v on supp(b)): per entry the cell
@@ -593,8 +747,8 @@ __device__ __forceinline__ double build_support(PairSmem<D>& s, const float* __r
     for (int c = c0; c < c1; ++c) {
       const float v = h[c];
       if (v > 0.0f) {
-        s.u.st.cell[off] = (c / d) * D + (c % d);
-        s.u.st.val[off] = v;
+        stCell<D>(s)[off] = (c / d) * D + (c % d);
+        stVal<D>(s)[off] = v;
         ++off;
       }
     }
@@ -607,9 +761,9 @@ __device__ __forceinline__ double build_support(PairSmem<D>& s, const float* __r
     const int e = threadIdx.x + PWGS * k;
     const bool ok = !too_big && e < total;
     if constexpr (SPT == 0) {
-      if (ok) sp.set_entry(k, s.u.st.cell[e], s.u.st.val[e]);
+      if (ok) sp.set_entry(k, stCell<D>(s)[e], stVal<D>(s)[e]);
     } else {
-      sp.set_entry(k, ok ? s.u.st.cell[e] : -1, ok ? s.u.st.val[e] : 0.0f);
+      sp.set_entry(k, ok ? stCell<D>(s)[e] : -1, ok ? stVal<D>(s)[e] : 0.0f);
     }
   }
   __syncthreads();
@@ -1067,6 +1221,9 @@ __device__ __forceinline__ void solve_pair(const PairParams& prm, PairSmem<D>& s
   const int tid = threadIdx.x;
   const int d = prm.d;
 
+  if constexpr (D > 128) {
+    if (tid == 0) s.gops = prm.ops + (size_t)blockIdx.x * GlobalOps<D>::BYTES;
+  }
   for (int x = tid; x < 2 * D; x += PWGS) {
     const bool in = x < 2 * D - 1;
     s.tge[x] = in ? prm.ge[x] : NEG;
@@ -1226,11 +1383,8 @@ __device__ __forceinline__ void solve_pair(const PairParams& prm, PairSmem<D>& s
   double g = 0.0;
   float* Wf = wbuf<D>(s, false);
   for (int pass = 0; pass < 2; ++pass) {
-    if (pass == 0) gemm_xk<D, false, false>(s, s.Qv, tri && !v_dense);
-    else gemm_xk<D, false, true>(s, s.Qv, tri && !v_dense);
-    __syncthreads();
-    if (pass == 0) gemm_kt<D, false, true>(s, s.Pv, Wf, tri);
-    else gemm_kt<D, false, false>(s, s.Pv, Wf, tri);
+    if (pass == 0) contract<D, false, false, true>(s, s.Pv, s.Qv, Wf, tri && !v_dense, tri);
+    else contract<D, false, true, false>(s, s.Pv, s.Qv, Wf, tri && !v_dense, tri);
 #pragma unroll
     for (int k = 0; k < nka; ++k) {
       const int c = ua.cell(k);
@@ -1318,7 +1472,7 @@ __device__ __forceinline__ void solve_pair(const PairParams& prm, PairSmem<D>& s
 template <int D, int SPT>
 __global__ __launch_bounds__(PWGS) void sinkhorn_pair_kernel(PairParams prm) {
   __shared__ PairSmem<D> s;
-  if constexpr (SPT > 0) {   // one pair per workgroup
+  if constexpr (SPT > 0 && D <= 128) {   // one pair per workgroup
     const long long pair = blockIdx.x;
     if (prm.only_redo && prm.redo[pair] != prm.only_redo) return;
     solve_pair<D, SPT>(prm, s, pair);

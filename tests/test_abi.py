@@ -54,7 +54,8 @@ def test_strerror_and_host_side_validation():
     out = ctypes.c_void_p()
     bad = [
         _lib.Params(1, 2.0, 1e-3, 1e-3, 100, 0, 1e-3),     # d < 2
-        _lib.Params(129, 2.0, 1e-3, 1e-3, 100, 0, 1e-3),   # d > 128
+        _lib.Params(257, 2.0, 1e-3, 1e-3, 100, 0, 1e-3),   # d > 256
+        _lib.Params(32, 2.0, 5e-6, 1e-3, 100, 0, 1e-3),    # gamma below the scale range
         _lib.Params(32, 0.5, 1e-3, 1e-3, 100, 0, 1e-3),    # p < 1
         _lib.Params(32, 2.0, 0.0, 1e-3, 100, 0, 1e-3),     # gamma <= 0
         _lib.Params(32, 2.0, 1e-3, -1.0, 100, 0, 1e-3),    # tol < 0

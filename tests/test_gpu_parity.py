@@ -61,7 +61,7 @@ def test_discretize_bit_exact(pds):
     edge = np.array([[0.0, 0.0], [1.0, 1.0], [0.5, 0.5], [np.nextafter(np.float32(0.5), np.float32(0)), 0.5],
                      [0.01, 0.99], [0.0, 1.0]], np.float32)
     diags = diags + [edge, np.zeros((0, 2), np.float32)]
-    for d in (2, 17, 32, 100, 128):
+    for d in (2, 17, 32, 100, 128, 200):
         with pds.Context(d, 1e-2) as ctx:
             pts, off = pdgen.to_csr(diags)
             hist, mass, bad = pds.pd_discretize(ctx, torch.from_numpy(pts).cuda(), torch.from_numpy(off).cuda())
@@ -317,3 +317,24 @@ def test_graph_capture_replays(pds):
             torch.cuda.synchronize()
             assert torch.equal(out.cost, ref.cost) and torch.equal(out.iters, ref.iters)
             assert torch.equal(out.err, ref.err) and torch.equal(out.status, ref.status)
+
+
+def test_grid_beyond_128_same_schedule(pds):
+    """d = 136 (operands in the global slice, 256-padded): FP32 costs against
+    the oracle at the GPU's iteration count, for pairs whose supports fit the
+    register lists and one that needs the global lists."""
+    d, g = 136, 5e-3
+    rng = np.random.default_rng(21)
+    small = [pdgen.gen(rng, 60), pdgen.gen(rng, 90)]
+    b = rng.random(3000)
+    big = np.stack([b, b + (1.0 - b) * rng.random(3000)], 1).astype(np.float32)
+    D1s, D2s = [small[0], big], [small[1], small[0]]
+    with pds.Context(d, g, tol=0.0, max_iter=25) as ctx:
+        cost, iters, err, st, hist = run_pairs(pds, ctx, D1s, D2s)
+    assert int((hist[1] > 0).sum()) > 512
+    C = dense_C(d)
+    for q in range(2):
+        assert iters[q].tolist() == [0, 25] and st[q] & ~1 == 0
+        r = sinkhorn.sinkhorn(hist[q], hist[2 + q], g, max_iter=25, C=C)
+        assert rel(cost[q], r.cost) <= FP32_RTOL, (q, cost[q], r.cost)
+    _C.pop(d, None)
