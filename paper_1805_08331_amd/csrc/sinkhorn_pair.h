@@ -427,8 +427,14 @@ __device__ __forceinline__ void gemm_xk(PairSmem<D>& s, const int* Q, bool trim)
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
       }
       mfma_drain();
+      // rows r = 4q .. 4q + 3 of the lane's accumulator are 4 consecutive k of
+      // Tt's row j: one 8-byte store each
 #pragma unroll
-      for (int r = 0; r < 16; ++r) s.u.b.Tt[j * LDB + tk * 32 + 8 * (r >> 2) + 4 * lk + (r & 3)] = (__bf16)acc[r];
+      for (int q = 0; q < 4; ++q) {
+        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+        const bf16x4 v = {(__bf16)acc[4 * q], (__bf16)acc[4 * q + 1], (__bf16)acc[4 * q + 2], (__bf16)acc[4 * q + 3]};
+        *reinterpret_cast<bf16x4*>(s.u.b.Tt + j * LDB + tk * 32 + 8 * q + 4 * lk) = v;
+      }
     } else {
       const int Sj = s.S[j];
 #pragma unroll 4
