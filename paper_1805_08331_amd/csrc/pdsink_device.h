@@ -38,20 +38,123 @@ __device__ __forceinline__ void mfma_drain() {
   __builtin_amdgcn_sched_barrier(0);
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+// Cross-lane steps without LDS traffic: DPP moves within rows of 16 lanes
+// (quad swaps, rotations, mirrors) and the gfx950 permlane swaps between
+// rows (lanes l and l ^ 16) and halves (l and l ^ 32).  Each reduction leaves
+// its result in every lane.
+constexpr int DPP_QXOR1 = 0xB1;     // quad_perm [1,0,3,2]
+constexpr int DPP_QXOR2 = 0x4E;     // quad_perm [2,3,0,1]
+constexpr int DPP_ROR4 = 0x124;     // row_ror:4
+constexpr int DPP_ROR8 = 0x128;     // row_ror:8
+constexpr int DPP_HMIRROR = 0x141;  // row_half_mirror: lane 7 - i within 8
+constexpr int DPP_MIRROR = 0x140;   // row_mirror: lane 15 - i within 16
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_i<CTRL>((int)(b & 0xffffffffLL)), hi = dpp_i<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+// The two values of lanes l and l ^ 16 (SWAP = 16) or l and l ^ 32 (SWAP = 32).
+template <int SWAP>
+__device__ __forceinline__ void swap_i(int v, int& a, int& b) {
+  if constexpr (SWAP == 16) {
+    const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    a = (int)p[0];
+    b = (int)p[1];
+  } else {
+    const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    a = (int)p[0];
+    b = (int)p[1];
+  }
+}
+template <int SWAP>
+__device__ __forceinline__ void swap_d(double v, double& a, double& b) {
+  const long long x = __double_as_longlong(v);
+  int la, lb, ha, hb;
+  swap_i<SWAP>((int)(x & 0xffffffffLL), la, lb);
+  swap_i<SWAP>((int)(x >> 32), ha, hb);
+  a = __longlong_as_double(((long long)(unsigned)ha << 32) | (unsigned)la);
+  b = __longlong_as_double(((long long)(unsigned)hb << 32) | (unsigned)lb);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_d<DPP_QXOR1>(v);
+  v += dpp_d<DPP_QXOR2>(v);
+  v += dpp_d<DPP_ROR4>(v);
+  v += dpp_d<DPP_ROR8>(v);
+  double a, b;
+  swap_d<16>(v, a, b);
+  v = a + b;
+  swap_d<32>(v, a, b);
+  return a + b;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+  v += dpp_f<DPP_QXOR1>(v);
+  v += dpp_f<DPP_QXOR2>(v);
+  v += dpp_f<DPP_ROR4>(v);
+  v += dpp_f<DPP_ROR8>(v);
+  int a, b;
+  swap_i<16>(__float_as_int(v), a, b);
+  v = __int_as_float(a) + __int_as_float(b);
+  swap_i<32>(__float_as_int(v), a, b);
+  return __int_as_float(a) + __int_as_float(b);
+}
+__device__ __forceinline__ int wave_sum(int v) {
+  v += dpp_i<DPP_QXOR1>(v);
+  v += dpp_i<DPP_QXOR2>(v);
+  v += dpp_i<DPP_ROR4>(v);
+  v += dpp_i<DPP_ROR8>(v);
+  int a, b;
+  swap_i<16>(v, a, b);
+  v = a + b;
+  swap_i<32>(v, a, b);
+  return a + b;
 }
 __device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-  return v;
+  v = max(v, dpp_i<DPP_QXOR1>(v));
+  v = max(v, dpp_i<DPP_QXOR2>(v));
+  v = max(v, dpp_i<DPP_ROR4>(v));
+  v = max(v, dpp_i<DPP_ROR8>(v));
+  int a, b;
+  swap_i<16>(v, a, b);
+  v = max(a, b);
+  swap_i<32>(v, a, b);
+  return max(a, b);
 }
 __device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  v = min(v, dpp_i<DPP_QXOR1>(v));
+  v = min(v, dpp_i<DPP_QXOR2>(v));
+  v = min(v, dpp_i<DPP_ROR4>(v));
+  v = min(v, dpp_i<DPP_ROR8>(v));
+  int a, b;
+  swap_i<16>(v, a, b);
+  v = min(a, b);
+  swap_i<32>(v, a, b);
+  return min(a, b);
+}
+// Maximum over aligned groups of N consecutive lanes (N = 4, 8, 16, 32), in
+// every lane of the group.
+template <int N>
+__device__ __forceinline__ int group_max(int v) {
+  static_assert(N == 4 || N == 8 || N == 16 || N == 32, "group size");
+  v = max(v, dpp_i<DPP_QXOR1>(v));
+  v = max(v, dpp_i<DPP_QXOR2>(v));
+  if constexpr (N >= 8) v = max(v, dpp_i<DPP_HMIRROR>(v));
+  if constexpr (N >= 16) v = max(v, dpp_i<DPP_MIRROR>(v));
+  if constexpr (N >= 32) {
+    int a, b;
+    swap_i<16>(v, a, b);
+    v = max(a, b);
+  }
   return v;
 }
 
@@ -94,13 +197,8 @@ __device__ __forceinline__ ESum esum_add(ESum a, ESum b) {
 // Sum over the wave: the largest exponent first, then one scaled sum, so the
 // shuffles carry plain doubles.  (A zero term has exponent NEG and vanishes.)
 __device__ __forceinline__ ESum wave_esum(ESum v) {
-  int e = v.s != 0.0 ? v.e : -(1 << 24);
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) e = max(e, __shfl_xor(e, o));
-  double x = v.s != 0.0 ? ldxd(v.s, v.e - e) : 0.0;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-  return ESum{e, x};
+  const int e = wave_max(v.s != 0.0 ? v.e : -(1 << 24));
+  return ESum{e, wave_sum(v.s != 0.0 ? ldxd(v.s, v.e - e) : 0.0)};
 }
 template <int NW = NWAVE>
 __device__ __forceinline__ ESum block_esum(ESum v, int* rede, double* reds) {

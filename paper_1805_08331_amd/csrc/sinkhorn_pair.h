@@ -282,12 +282,11 @@ __device__ __forceinline__ void compute_RS(PairSmem<D>& s, const int* P, const i
       w0 = tw[-(t + 1)];
     }
   }
-#pragma unroll
-  for (int o = 1; o < NPART; o <<= 1) {
-    b0 = max(b0, __shfl_xor(b0, o));
-    b1 = max(b1, __shfl_xor(b1, o));
-    b2 = max(b2, __shfl_xor(b2, o));
-    b3 = max(b3, __shfl_xor(b3, o));
+  if constexpr (NPART > 1) {
+    b0 = group_max<NPART>(b0);
+    b1 = group_max<NPART>(b1);
+    b2 = group_max<NPART>(b2);
+    b3 = group_max<NPART>(b3);
   }
   if (part == 0) {
     int* out = (rows ? s.R : s.S) + i0;
