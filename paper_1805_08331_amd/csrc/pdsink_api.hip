@@ -125,7 +125,7 @@ struct PairExtras {
   double* gout = nullptr;     // [n_pairs][d * d] gradient terms
 };
 
-size_t list_bytes(int D) { return align256((size_t)40 * D * D); }   // 2 sides x 5 arrays x D^2 x 4 bytes
+size_t list_bytes(int D) { return align256((size_t)52 * D * D); }   // 2 sides x 5 arrays + 3 suspect arrays, x D^2 x 4 bytes
 size_t warm_bytes(int D) {
   switch (D) {
     case 32: return sizeof(WarmState<32>);

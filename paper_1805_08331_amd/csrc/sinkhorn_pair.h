@@ -166,6 +166,7 @@ struct PairSmem : OpsLds<D> {
   int susp_cell[MAXSUSP];
   int susp_e[MAXSUSP];     // value = susp_m * 2^susp_e (natural scale, or absolute for the cost)
   float susp_m[MAXSUSP];
+  int* gsusp;              // global-list variant: suspect arrays of capacity D^2 in the workspace
   int xs_cell[PWGS];       // staging of a register support list for the exact path
   float xs_res[PWGS];
   char* gops;              // global operand slice (grids beyond 128)
@@ -220,6 +221,28 @@ template <int D>
 __device__ __forceinline__ float* wbuf(PairSmem<D>& s, bool bf16) {
   if constexpr (D <= 128) return bf16 ? reinterpret_cast<float*>(s.u.b.Tt) : s.u.f.T;
   else return reinterpret_cast<float*>(s.gops + GlobalOps<D>::W);
+}
+
+// Suspect arrays: in LDS (MAXSUSP entries) for register lists; in the
+// workspace slot (D^2 entries: every cell can be one) for global lists.
+template <int D, int SPT>
+__device__ __forceinline__ int* suspCell(PairSmem<D>& s) {
+  if constexpr (SPT > 0) return s.susp_cell;
+  else return s.gsusp;
+}
+template <int D, int SPT>
+__device__ __forceinline__ int* suspE(PairSmem<D>& s) {
+  if constexpr (SPT > 0) return s.susp_e;
+  else return s.gsusp + D * D;
+}
+template <int D, int SPT>
+__device__ __forceinline__ float* suspM(PairSmem<D>& s) {
+  if constexpr (SPT > 0) return s.susp_m;
+  else return reinterpret_cast<float*>(s.gsusp + 2 * D * D);
+}
+template <int D, int SPT>
+__device__ __forceinline__ constexpr int suspCap() {
+  return SPT > 0 ? MAXSUSP : D * D;
 }
 
 // Kernel headroom for an input whose residual spans +-mres octaves.
@@ -847,7 +870,7 @@ __device__ __forceinline__ void exact_all(PairSmem<D>& s, const SupList<SPT>& xs
         eb[u] = ok ? Px[kr[u]] + Qx[l[u]] : QNONE;
       }
       for (int id = wave; id < ns; id += PNW) {
-        const int c = s.susp_cell[id];
+        const int c = suspCell<D, SPT>(s)[id];
         const int ti = c / D, tj = c % D;
         int em = QNONE;
 #pragma unroll
@@ -872,10 +895,18 @@ __device__ __forceinline__ void exact_all(PairSmem<D>& s, const SupList<SPT>& xs
       return;
     }
   }
-  for (int id = wave; id < ns; id += PNW) {
-    const int c = s.susp_cell[id];
-    const int ti = c / D, tj = c % D;
-    int em = QNONE;
+  // Four suspects per wave, so that each entry of x is read once for four.
+  constexpr int NT4 = 4;
+  for (int id0 = wave * NT4; id0 < ns; id0 += PNW * NT4) {
+    const int nt = min(NT4, ns - id0);
+    int ti[NT4], tj[NT4], em[NT4];
+#pragma unroll
+    for (int t = 0; t < NT4; ++t) {
+      const int c = t < nt ? suspCell<D, SPT>(s)[id0 + t] : 0;
+      ti[t] = c / D;
+      tj[t] = c % D;
+      em[t] = QNONE;
+    }
     for (int e = lane; e < nx; e += 64) {
       int cell;
       float x;
@@ -888,11 +919,15 @@ __device__ __forceinline__ void exact_all(PairSmem<D>& s, const SupList<SPT>& xs
       }
       if (cell >= 0 && x > 0.0f) {
         const int kr = cell / D, l = cell % D;
-        em = max(em, Px[kr] + Qx[l] + ilog2f(x) + s.tge[ti - kr + D - 1] + s.tge[tj - l + D - 1]);
+        const int eb = Px[kr] + Qx[l] + ilog2f(x);
+#pragma unroll
+        for (int t = 0; t < NT4; ++t)
+          em[t] = max(em[t], eb + s.tge[ti[t] - kr + D - 1] + s.tge[tj[t] - l + D - 1]);
       }
     }
-    em = wave_max(em);
-    float acc = 0.0f;
+#pragma unroll
+    for (int t = 0; t < NT4; ++t) em[t] = wave_max(em[t]);
+    float acc[NT4] = {0.0f, 0.0f, 0.0f, 0.0f};
     for (int e = lane; e < nx; e += 64) {
       int cell;
       float x;
@@ -905,14 +940,23 @@ __device__ __forceinline__ void exact_all(PairSmem<D>& s, const SupList<SPT>& xs
       }
       if (cell >= 0 && x > 0.0f) {
         const int kr = cell / D, l = cell % D;
-        const int i1 = ti - kr + D - 1, i2 = tj - l + D - 1;
-        float mm = x * s.tgm[i1] * s.tgm[i2];
-        if (WEIGHTED) mm *= (s.tc1[i1] + s.tc1[i2]);
-        acc += ldx(mm, Px[kr] + Qx[l] + s.tge[i1] + s.tge[i2] - em);
+        const int eb = Px[kr] + Qx[l];
+#pragma unroll
+        for (int t = 0; t < NT4; ++t) {
+          const int i1 = ti[t] - kr + D - 1, i2 = tj[t] - l + D - 1;
+          float mm = x * s.tgm[i1] * s.tgm[i2];
+          if (WEIGHTED) mm *= (s.tc1[i1] + s.tc1[i2]);
+          acc[t] += ldx(mm, eb + s.tge[i1] + s.tge[i2] - em[t]);
+        }
       }
     }
-    acc = wave_sum(acc);
-    if (lane == 0) finish(id, c, em, acc);
+#pragma unroll
+    for (int t = 0; t < NT4; ++t) acc[t] = wave_sum(acc[t]);
+    if (lane == 0) {
+#pragma unroll
+      for (int t = 0; t < NT4; ++t)
+        if (t < nt) finish(id0 + t, ti[t] * D + tj[t], em[t], acc[t]);
+    }
   }
   __syncthreads();
 }
@@ -999,8 +1043,8 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, bool w
       bool sus = false;
       if (le < thr) {
         const int id = atomicAdd(&s.nsusp, 1);
-        if (id < MAXSUSP) {
-          s.susp_cell[id] = c;
+        if (id < suspCap<D, SPT>()) {
+          suspCell<D, SPT>(s)[id] = c;
           qk = QSUSP + id;
           sus = true;
         } else {
@@ -1053,7 +1097,7 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, bool w
     }
   }
   __syncthreads();
-  const int ns = min(s.nsusp, MAXSUSP);
+  const int ns = min(s.nsusp, suspCap<D, SPT>());
   double egs = 0.0;
   int flags = 0;
 #pragma unroll
@@ -1064,7 +1108,8 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, bool w
 
   // Suspects: exact values, then their row extrema and error terms.
   if (ns > 0) {
-    exact_all<D, SPT, false, true>(s, xsup, x_dense, d, Px, Qx, ns, s.susp_e, s.susp_m, true, xs.ex, mxf);
+    exact_all<D, SPT, false, true>(s, xsup, x_dense, d, Px, Qx, ns, suspE<D, SPT>(s), suspM<D, SPT>(s), true, xs.ex,
+                                   mxf);
     double eg2 = 0.0;
 #pragma unroll
     for (int k = 0; k < nk; ++k) {
@@ -1073,13 +1118,13 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, bool w
         const int id = qk - QSUSP;
         const int c = ys.cell(k), i = c / D, j = c % D;
         const float tg = ys.tgt(k);
-        const int qx = ilog2f(tg) - (s.susp_e[id] + ilog2f(s.susp_m[id]));
+        const int qx = ilog2f(tg) - (suspE<D, SPT>(s)[id] + ilog2f(suspM<D, SPT>(s)[id]));
         ys.set_qe(k, qx);
         atomicMax(&s.fit[0][0][i], qx);
         atomicMin(&s.fit[0][1][i], qx);
         if (check) {
           const int sh = Py[i] + Qy[j] + s.R[i] + s.S[j];
-          const double row = ldxd((double)ys.res(k) * (double)s.susp_m[id], s.susp_e[id] + sh);
+          const double row = ldxd((double)ys.res(k) * (double)suspM<D, SPT>(s)[id], suspE<D, SPT>(s)[id] + sh);
           eg2 += fabs(row - (double)tg);
         }
       }
@@ -1164,7 +1209,7 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, bool w
       float y;
       if (qk >= QSUSP) {
         const int id = qk - QSUSP;
-        y = tg / ldx(s.susp_m[id], s.susp_e[id] + sh);
+        y = tg / ldx(suspM<D, SPT>(s)[id], suspE<D, SPT>(s)[id] + sh);
       } else {
         const int E = xs.ex + s.tgde[dl] - s.R[i] - s.S[j];
         const float Dm = mxf * s.tgdm[dl];
@@ -1250,6 +1295,7 @@ __device__ __forceinline__ void solve_pair(const PairParams& prm, PairSmem<D>& s
     base += 5 * CAP;
     vb = SupList<0>{base, reinterpret_cast<float*>(base + CAP), reinterpret_cast<float*>(base + 2 * CAP),
                     base + 3 * CAP, base + 4 * CAP, 0, CAP};
+    if (tid == 0) s.gsusp = base + 5 * CAP;   // suspect arrays after the two lists
   }
   bool big_a, big_b, low_a, low_b;
   const double mA = build_support<D, SPT>(s, A, d, ua, big_a, low_a);
@@ -1403,9 +1449,9 @@ __device__ __forceinline__ void solve_pair(const PairParams& prm, PairSmem<D>& s
     }
     __syncthreads();
   }
-  const int ns = bad ? 0 : min(s.nsusp, MAXSUSP);
+  const int ns = bad ? 0 : min(s.nsusp, suspCap<D, SPT>());
   if (ns > 0) {
-    exact_all<D, SPT, true, false>(s, vb, v_dense, d, s.Pv, s.Qv, ns, s.susp_e, s.susp_m);
+    exact_all<D, SPT, true, false>(s, vb, v_dense, d, s.Pv, s.Qv, ns, suspE<D, SPT>(s), suspM<D, SPT>(s));
 #pragma unroll
     for (int k = 0; k < nka; ++k) {
       const int qk = ua.q(k);
@@ -1414,7 +1460,7 @@ __device__ __forceinline__ void solve_pair(const PairParams& prm, PairSmem<D>& s
         if (r > 0.0f) {
           const int c = ua.cell(k), i = c / D, j = c % D;
           const int id = qk - QSUSP;
-          g += ldxd((double)r * (double)s.susp_m[id], s.susp_e[id] + s.Pu[i] + s.Qu[j]);
+          g += ldxd((double)r * (double)suspM<D, SPT>(s)[id], suspE<D, SPT>(s)[id] + s.Pu[i] + s.Qu[j]);
         }
       }
     }

@@ -168,8 +168,8 @@ def test_edge_cases(pds):
 
 
 def test_support_size_levels(pds):
-    """Pairs whose supports exceed 512 and 1024 cells (re-run by the wider
-    compact variant and by the dense kernel) match the oracle like small ones."""
+    """Pairs whose supports exceed 512 cells (re-run with support lists in
+    global memory) match the oracle like small ones."""
     d, g = 64, 5e-3
     rng = np.random.default_rng(11)
 
@@ -190,6 +190,30 @@ def test_support_size_levels(pds):
         assert st[q] == 0 and err[q] <= 1e-4, (q, st[q], err[q])
         r = sinkhorn.sinkhorn(hist[q], hist[n + q], g, max_iter=int(iters[q].sum()), C=C)
         assert rel(cost[q], r.cost) <= FP32_RTOL, (q, supp[q], supp[n + q], cost[q], r.cost)
+
+
+@pytest.mark.parametrize("d", [64, 100])
+def test_dense_centroid_same_schedule(pds, d):
+    """A fully dense upper-triangular histogram (the shape of a barycenter)
+    against diagrams, in both argument orders: every cell can hold a suspect
+    value, so this exercises suspect lists far beyond the register-list path."""
+    g = 1e-3
+    D1s, _ = pdgen.pairs_batch(4, 3, 50, 300)
+    hists = [ground.discretize(x, d) for x in D1s]
+    z = np.triu(np.ones((d, d))) * np.mean([h.sum() for h in hists]) / (d * (d + 1) / 2)
+    A = torch.from_numpy(np.stack([z] + hists).astype(np.float32)).cuda()
+    z32 = A[0].cpu().numpy().astype(np.float64)
+    ia = torch.tensor([0, 0, 0, 1, 2, 3], dtype=torch.int32, device="cuda")
+    ib = torch.tensor([1, 2, 3, 0, 0, 0], dtype=torch.int32, device="cuda")
+    with pds.Context(d, g, tol=1e-4, max_iter=3000) as ctx:
+        r = pds.sinkhorn_dist_batch(ctx, A, A, ia, ib)
+        torch.cuda.synchronize()
+    st, iters, cost = r.status.cpu().numpy(), r.iters.cpu().numpy(), r.cost.cpu().numpy()
+    for q in range(6):
+        a, b = (z32, hists[q]) if q < 3 else (hists[q - 3], z32)
+        assert st[q] == 0 and float(r.err[q]) <= 1e-4, (q, st[q], float(r.err[q]))
+        o = sinkhorn.sinkhorn(a, b, g, max_iter=int(iters[q].sum()), C=dense_C(d))
+        assert rel(cost[q], o.cost) <= FP32_RTOL, (q, cost[q], o.cost)
 
 
 def test_alone_equals_in_batch(pds):
