@@ -25,6 +25,9 @@ What it computes (Lacombe, Cuturi, Oudot, NeurIPS 2018):
                     gradient of Proposition 5).
 * ``kmeans``      - section 5 k-means: assignment by Algorithm 1, centroids
                     by Algorithm 2.
+* ``bounds``      - error control of section 3: the upper bound <R_t, C> of
+                    the rounded plan (rounding algorithm of the supplementary
+                    material, Proposition 4) and the c-transform lower bound.
 
 Every function that has no pin to something other than itself says
 "parity unpinned" in its docstring.
