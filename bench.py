@@ -174,6 +174,52 @@ def measured_traffic():
     return rec.get("traffic_bytes") if rec.get("source_hash") == source_hash() else None
 
 
+def write_traffic(fetch_csv: str, write_csv: str):
+    """Summarise two rocprofv3 counter runs of ``--pmc-probe`` (FETCH_SIZE, then
+    WRITE_SIZE, KiB per dispatch) into the traffic record of the pair kernel,
+    scaled by what the counters read for the 256 MiB calibration copy."""
+    import csv
+
+    def rows(path, counter):
+        with open(path, newline="") as fh:
+            return [(r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"]))
+                    for r in csv.DictReader(fh) if r["Counter_Name"] == counter]
+
+    fr, wr = rows(fetch_csv, "FETCH_SIZE"), rows(write_csv, "WRITE_SIZE")
+    if len(fr) != len(wr):
+        raise SystemExit("the two counter runs saw different dispatch lists")
+    copy_bytes = 256 << 20
+    copy = [i for i, (n, g, v) in enumerate(fr) if n.startswith("__amd_rocclr_copyBuffer")]
+    ci = max(copy, key=lambda i: fr[i][2])
+    kern = [i for i, (n, g, v) in enumerate(fr) if "sinkhorn_pair_kernel<128, 1" in n and g == NPAIRS * 512]
+    if len(kern) != 1:
+        raise SystemExit("expected one level-0 launch of the pair kernel")
+    ki = kern[0]
+    ff = copy_bytes / 1024 / fr[ci][2]
+    wf = copy_bytes / 1024 / wr[ci][2]
+    traffic = (fr[ki][2] * ff + wr[ki][2] * wf) * 1024
+    rec = {"kernel": "sinkhorn_pair_kernel<128, 1, false>",
+           "workload": "1024 PD pairs, d=100, gamma=1e-3, tol=1e-3, BF16+FP32 refinement",
+           "source_hash": source_hash(), "fetch_kib_raw": fr[ki][2], "write_kib_raw": wr[ki][2],
+           "copy_calibration": {"bytes": copy_bytes, "fetch_kib_raw": fr[ci][2], "write_kib_raw": wr[ci][2],
+                                "fetch_factor": ff, "write_factor": wf},
+           "traffic_bytes": int(round(traffic)),
+           # two d x d FP32 histograms per pair in; cost, 2 iteration counts, error, status, route byte out
+           "algorithmic_bytes": NPAIRS * (2 * 100 * 100 * 4 + 8 + 8 + 4 + 4 + 1)}
+    out = os.path.join(ROOT, "profiles", "sinkhorn_pair_kernel_d100_1024pairs_traffic.json")
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    print("| dispatch | grid | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) |")
+    print("|---|---|---|---|")
+    for (n, g, v), (_, _, w) in zip(fr, wr):
+        if n.startswith("__amd_rocclr_copyBuffer") and g < 1 << 16:
+            continue
+        short = n.replace("void ", "").replace("(anonymous namespace)::", "").split("(")[0][:60]
+        print(f"| `{short}` | {g} | {v:.1f} | {w:.1f} |")
+    print(json.dumps(rec))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,7 +231,12 @@ def main():
                     help="run one BF16 batch and a 256 MiB device copy (for counter runs), then exit")
     ap.add_argument("--switch-tol", type=float, default=1.1e-3,
                     help="BF16 -> FP32 switch point of the marginal error (1.1 x tol)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the traffic record from two --pmc-probe counter runs, then exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic(*args.traffic_from)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the per-GPU shard is the batch measured at --gpus 1)", file=sys.stderr)
@@ -257,7 +308,7 @@ def main():
                        "of": "one 1024-pair batch (discretise + Algorithm 1 + cost)"},
         "roofline": {"bound": "mfma", "achieved": m["achieved_tflops"], "peak": m["peak_tflops"], "unit": "TFLOP/s",
                      "frac": m["achieved_tflops"] / m["peak_tflops"], "traffic": measured_traffic(),
-                     "kernel": "sinkhorn_pair_kernel<128, 1>", "kernel_ms": k_avg * 1e3},
+                     "kernel": "sinkhorn_pair_kernel<128, 1, false>", "kernel_ms": k_avg * 1e3},
     }
     if "fp32" in res and main_key == "bf16":
         f = res["fp32"]

@@ -119,13 +119,35 @@ int pd_discretize(pdsink_ctx* ctx, const float* pts, const int64_t* offsets, int
  *   ws, ws_bytes   (device) workspace of at least pdsink_workspace_bytes(DIST, n_pairs)
  *                  bytes (one routing byte per pair); PDSINK_ENOMEM if smaller
  * Masses are the histogram sums.  n_pairs = 0 is a no-op.  Any support size
- * is accepted: pairs whose supports exceed the compact kernel's lists run in a
- * dense kernel, from the same launch sequence. */
+ * is accepted: pairs whose supports exceed the register lists (512 cells per
+ * side) run again with their lists in the workspace, from the same launch
+ * sequence. */
 int sinkhorn_dist_batch(pdsink_ctx* ctx, int64_t n_pairs,
                         const float* hist_a, const float* hist_b,
                         const int32_t* ia, const int32_t* ib,
                         double* cost, int32_t* iters, float* err, int32_t* status,
                         void* ws, size_t ws_bytes, void* stream);
+
+/* sinkhorn_dist_batch plus the error control of section 3 ("Upper and Lower
+ * Bounds"; Algorithm 1's optional outputs) for the final (u_t, v_t):
+ *   upper (device) double [n_pairs] out, may be NULL: <R_t, C>, R_t the
+ *         rounding of P_t = diag(u_t) K diag(v_t) onto Pi(a, b) (rounding
+ *         algorithm of the supplementary material), priced by Proposition 4
+ *   lower (device) double [n_pairs] out, may be NULL: <alpha^{c cbar}, a> +
+ *         <alpha^c, b> with alpha = gamma log u_t, both c-transforms (inf over
+ *         the ground space, every grid cell and the diagonal bin) computed
+ *         by separable min-plus passes over the grid
+ * so that lower <= L_C(a, b) <= upper up to rounding.  Both are NaN for a pair
+ * whose status has PDSINK_ST_NONFINITE, and 0 for an empty pair.  The K
+ * applications inside are exact sums over the two supports, O(|supp a| |supp b|)
+ * per pair; the transforms cost O(d^3) per pair.  Other arguments, errors and
+ * the workspace are those of sinkhorn_dist_batch. */
+int sinkhorn_dist_bounds_batch(pdsink_ctx* ctx, int64_t n_pairs,
+                               const float* hist_a, const float* hist_b,
+                               const int32_t* ia, const int32_t* ib,
+                               double* cost, int32_t* iters, float* err, int32_t* status,
+                               double* upper, double* lower,
+                               void* ws, size_t ws_bytes, void* stream);
 
 /* Algorithm 2: smoothed barycenter of the diagrams hist[0..n_diag) (section 4).
  * Pairs (z + R a_i, a_i + R z) are iterated to `tol` of the context

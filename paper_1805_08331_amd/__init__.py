@@ -131,12 +131,17 @@ class DistResult:
     iters: torch.Tensor     # int32 [n, 2]: BF16 iterations, FP32 iterations
     err: torch.Tensor       # float32 [n]
     status: torch.Tensor    # int32 [n]
+    upper: torch.Tensor | None = None   # float64 [n]: <R_t, C> of the rounded plan (bounds=True)
+    lower: torch.Tensor | None = None   # float64 [n]: c-transform dual bound (bounds=True)
 
 
 def sinkhorn_dist_batch(ctx: Context, hist_a: torch.Tensor, hist_b: torch.Tensor, ia: torch.Tensor,
                         ib: torch.Tensor, out: DistResult | None = None, ws: torch.Tensor | None = None,
-                        check_indices: bool = True) -> DistResult:
+                        check_indices: bool = True, bounds: bool = False) -> DistResult:
     """Algorithm 1 on pairs (hist_a[ia[q]], hist_b[ib[q]]).
+
+    ``bounds`` also returns the error-control bounds of section 3 in
+    ``upper`` and ``lower`` (lower <= exact transport value <= upper).
 
     ``check_indices`` reads the index ranges back to the host (a stream
     synchronisation); pass False inside graph capture, where the caller
@@ -161,6 +166,15 @@ def sinkhorn_dist_batch(ctx: Context, hist_a: torch.Tensor, hist_b: torch.Tensor
                          torch.empty(n, dtype=torch.int32, device=dev))
     if ws is None:
         ws = ctx.workspace(_lib.PDSINK_OP_DIST, n)
+    if bounds:
+        if out.upper is None:
+            out.upper = torch.empty(n, dtype=torch.float64, device=dev)
+        if out.lower is None:
+            out.lower = torch.empty(n, dtype=torch.float64, device=dev)
+        _lib.check("sinkhorn_dist_bounds_batch", _lib.load().sinkhorn_dist_bounds_batch(
+            ctx.handle, n, _vp(hist_a), _vp(hist_b), _vp(ia), _vp(ib), _vp(out.cost), _vp(out.iters),
+            _vp(out.err), _vp(out.status), _vp(out.upper), _vp(out.lower), _vp(ws), ws.numel(), _stream()))
+        return out
     _lib.check("sinkhorn_dist_batch", _lib.load().sinkhorn_dist_batch(
         ctx.handle, n, _vp(hist_a), _vp(hist_b), _vp(ia), _vp(ib), _vp(out.cost), _vp(out.iters),
         _vp(out.err), _vp(out.status), _vp(ws), ws.numel(), _stream()))

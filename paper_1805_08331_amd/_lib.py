@@ -59,6 +59,8 @@ SIGNATURES = {
     "pd_discretize": (c_int, [c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp]),
     "sinkhorn_dist_batch": (c_int, [c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
                                     c_vp, c_size, c_vp]),
+    "sinkhorn_dist_bounds_batch": (c_int, [c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
+                                           c_vp, c_vp, c_vp, c_size, c_vp]),
     "pd_barycenter": (c_int, [c_vp, c_i64, c_vp, c_dbl, c_i32, c_dbl, c_i32, c_vp,
                               ctypes.POINTER(c_dbl), ctypes.POINTER(c_i32), c_vp, c_size, c_vp]),
     "kmeans_assign": (c_int, [c_vp, c_i64, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_size, c_vp]),

@@ -1,7 +1,9 @@
 """Build the pdsink HIP library in-tree for gfx950 with hipcc.
 
 ``python -m paper_1805_08331_amd.build`` (or ``build()``) compiles
-``csrc/pdsink_api.hip`` (which includes the kernel headers) into
+``csrc/pdsink_api.hip`` (the C ABI and the plain kernels) and
+``csrc/pdsink_bounds.hip`` (the kernel variant with the error-control bounds),
+both of which include the kernel headers, into
 ``paper_1805_08331_amd/libpdsink.so``.  It always recompiles.
 """
 from __future__ import annotations
@@ -13,7 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdsink.so")
-SOURCES = ["pdsink_api.hip", "barycenter.hip"]
+SOURCES = ["pdsink_api.hip", "pdsink_bounds.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

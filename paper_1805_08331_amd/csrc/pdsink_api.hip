@@ -12,9 +12,13 @@
 #include "../../include/pdsink.h"
 #include "pdsink_device.h"
 #include "sinkhorn_pair.h"
-#include "sinkhorn_pair.h"
 
 using namespace pdsink;
+
+namespace pdsink {
+// The bounds variant of the pair kernel (pdsink_bounds.hip).
+int launch_pair_bounds(int D, PairParams pp, int n_slots, hipStream_t st);
+}  // namespace pdsink
 
 
 
@@ -123,6 +127,8 @@ struct PairExtras {
   char* state = nullptr;      // WarmState per pair
   int state_in = 0;
   double* gout = nullptr;     // [n_pairs][d * d] gradient terms
+  double* upper = nullptr;    // [n_pairs] error-control bounds
+  double* lower = nullptr;
 };
 
 size_t list_bytes(int D) { return align256((size_t)52 * D * D); }   // 2 sides x 5 arrays + 3 suspect arrays, x D^2 x 4 bytes
@@ -147,6 +153,7 @@ int64_t slots_for(const pdsink_ctx* ctx, int64_t n_pairs) { return n_pairs < ctx
 // second launch only reads the flags.
 template <int D>
 int launch_levels(PairParams pp, int n_slots, hipStream_t st) {
+  if (pp.upper || pp.lower) return launch_pair_bounds(D, pp, n_slots, st) ? PDSINK_EDEVICE : PDSINK_OK;
   pp.only_redo = 0;
   // beyond D = 128 every launch strides over the batch with one operand slice per slot
   const unsigned g0 = D > 128 ? (unsigned)n_slots : (unsigned)pp.n_pairs;
@@ -190,6 +197,10 @@ int run_pairs(const pdsink_ctx* ctx, int64_t n_pairs, const float* ha, const flo
   pp.state = ex.state;
   pp.state_in = ex.state_in;
   pp.gout = ex.gout;
+  pp.upper = ex.upper;
+  pp.lower = ex.lower;
+  pp.gamma = ctx->prm.gamma;
+  pp.p = ctx->prm.p;
   switch (ctx->D) {
     case 32: return launch_levels<32>(pp, ex.n_slots, st);
     case 64: return launch_levels<64>(pp, ex.n_slots, st);
@@ -415,6 +426,14 @@ int pd_discretize(pdsink_ctx* ctx, const float* pts, const int64_t* offsets, int
 int sinkhorn_dist_batch(pdsink_ctx* ctx, int64_t n_pairs, const float* hist_a, const float* hist_b,
                         const int32_t* ia, const int32_t* ib, double* cost, int32_t* iters, float* err,
                         int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+  return sinkhorn_dist_bounds_batch(ctx, n_pairs, hist_a, hist_b, ia, ib, cost, iters, err, status, nullptr,
+                                    nullptr, ws, ws_bytes, stream);
+}
+
+int sinkhorn_dist_bounds_batch(pdsink_ctx* ctx, int64_t n_pairs, const float* hist_a, const float* hist_b,
+                               const int32_t* ia, const int32_t* ib, double* cost, int32_t* iters, float* err,
+                               int32_t* status, double* upper, double* lower, void* ws, size_t ws_bytes,
+                               void* stream) {
   if (!ctx || n_pairs < 0) return PDSINK_EINVAL;
   if (n_pairs == 0) return PDSINK_OK;
   if (n_pairs > INT_MAX || !hist_a || !hist_b || !ia || !ib || !cost || !iters || !err || !status)
@@ -428,6 +447,8 @@ int sinkhorn_dist_batch(pdsink_ctx* ctx, int64_t n_pairs, const float* hist_a, c
   ex.n_slots = (int)slots_for(ctx, n_pairs);
   ex.lists = (char*)ws + align256(n_pairs);
   ex.ops = ex.lists + ex.n_slots * list_bytes(ctx->D);
+  ex.upper = upper;
+  ex.lower = lower;
   return run_pairs(ctx, n_pairs, hist_a, hist_b, ia, ib, cost, iters, err, status, (unsigned char*)ws, ex,
                    (hipStream_t)stream);
 }

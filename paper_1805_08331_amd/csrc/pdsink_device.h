@@ -141,6 +141,17 @@ __device__ __forceinline__ int wave_min(int v) {
   swap_i<32>(v, a, b);
   return min(a, b);
 }
+__device__ __forceinline__ double wave_min(double v) {
+  v = fmin(v, dpp_d<DPP_QXOR1>(v));
+  v = fmin(v, dpp_d<DPP_QXOR2>(v));
+  v = fmin(v, dpp_d<DPP_ROR4>(v));
+  v = fmin(v, dpp_d<DPP_ROR8>(v));
+  double a, b;
+  swap_d<16>(v, a, b);
+  v = fmin(a, b);
+  swap_d<32>(v, a, b);
+  return fmin(a, b);
+}
 // Maximum over aligned groups of N consecutive lanes (N = 4, 8, 16, 32), in
 // every lane of the group.
 template <int N>
@@ -168,6 +179,17 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   double t = 0.0;
 #pragma unroll 4
   for (int w = 0; w < NW; ++w) t += red[w];
+  return t;
+}
+template <int NW = NWAVE>
+__device__ __forceinline__ double block_min(double v, double* red) {
+  v = wave_min(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = red[0];
+#pragma unroll 4
+  for (int w = 1; w < NW; ++w) t = fmin(t, red[w]);
   return t;
 }
 template <int NW = NWAVE>

@@ -91,6 +91,12 @@ struct PairParams {
   // optional gradient terms of Proposition 5, [n_pairs][d * d]: log u + log
   // v_Delta on the cells of supp(a)
   double* gout;
+  // optional error-control bounds of section 3 per pair (upper: rounded plan,
+  // lower: c-transform dual), with the ground exponent and gamma they need
+  double* upper;
+  double* lower;
+  double gamma;
+  double p;
 };
 
 constexpr int PWGS = 512;      // threads per pair workgroup
@@ -156,7 +162,7 @@ struct PairSmem : OpsLds<D> {
   alignas(16) int Qv[D];
   int R[D], S[D];
   // refit extrema: [sweep][row max, row min, column max, column min][D]
-  int fit[2][4][D];
+  alignas(16) int fit[2][4][D];   // also the FP64 cost tables of the bounds
   int sflag;               // bit 0: a suspect's exact value vanished
   double red[PNW];
   double reds[PNW];
@@ -1266,7 +1272,305 @@ struct WarmState {
   double vmx;
 };
 
+// ---------------------------------------------------------------------------
+// Error control of section 3, after the last iteration: an upper bound from
+// the rounding of the plan onto the transport polytope (Proposition 4, with
+// the rounding algorithm of the supplementary material) and a lower bound
+// from the c-transforms of alpha = gamma log u.
+
+// Number of entries of a support list (register lists hold at most one per
+// thread, in threads 0, 1, ...).
+template <int SPT>
+__device__ __forceinline__ int list_len(const SupList<SPT>& l) {
+  if constexpr (SPT == 0) return l.n;
+  else return __syncthreads_count(l.cell(0) >= 0);
+}
+
+// (K x)_c, or ((K o C) x)_c when WEIGHTED, grid part only, at every entry c
+// of ys, summed exactly over the support of x (exact_all).  The value of
+// entry k is m * 2^e, left as ys.q(k) = e and ys.qe(k) = the bits of m.
+// Register lists pass through the LDS suspect arrays MAXSUSP entries at a time.
+template <int D, int SPT, bool WEIGHTED>
+__device__ __forceinline__ void sparse_kx(PairSmem<D>& s, SupList<SPT>& ys, const SupList<SPT>& xs, const int* Px,
+                                          const int* Qx, int d, int ny) {
+  if constexpr (SPT == 1) {
+    for (int c0 = 0; c0 < ny; c0 += MAXSUSP) {
+      const int id = (int)threadIdx.x - c0;
+      const bool mine = id >= 0 && id < MAXSUSP && ys.cell(0) >= 0;
+      if (mine) s.susp_cell[id] = ys.cell(0);
+      __syncthreads();
+      exact_all<D, 1, WEIGHTED, false>(s, xs, false, d, Px, Qx, min(MAXSUSP, ny - c0), s.susp_e, s.susp_m);
+      if (mine) {
+        ys.set_q(0, s.susp_e[id]);
+        ys.set_qe(0, __float_as_int(s.susp_m[id]));
+      }
+      __syncthreads();
+    }
+  } else {
+    for (int k = 0; k < ys.nk(); ++k)
+      if (ys.ix(k) < ny) suspCell<D, 0>(s)[ys.ix(k)] = ys.cell(k);
+    __syncthreads();
+    exact_all<D, 0, WEIGHTED, false>(s, xs, false, d, Px, Qx, ny, suspE<D, 0>(s), suspM<D, 0>(s));
+    for (int k = 0; k < ys.nk(); ++k) {
+      if (ys.ix(k) < ny) {
+        ys.set_q(k, suspE<D, 0>(s)[ys.ix(k)]);
+        ys.set_qe(k, __float_as_int(suspM<D, 0>(s)[ys.ix(k)]));
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// y (K x)_c at entry k of ys from sparse_kx's value, plus the diagonal-bin
+// term y x_Delta k_Delta(c): a marginal of the plan, in the natural range.
 template <int D, int SPT>
+__device__ __forceinline__ double marg_at(const PairSmem<D>& s, const SupList<SPT>& ys, int k, float yres,
+                                          const int* Py, const int* Qy, int xD_e, double xD_m) {
+  const int c = ys.cell(k), i = c / D, j = c % D, dl = j - i + D - 1;
+  const int e0 = Py[i] + Qy[j];
+  return ldxd((double)yres * (double)__int_as_float(ys.qe(k)), e0 + ys.q(k)) +
+         ldxd((double)yres * xD_m * (double)s.tgdm[dl], e0 + xD_e + s.tgde[dl]);
+}
+
+// In place over the rows (ROWS) or columns of the d x d part of g (row stride
+// D + 1): g[r][o] <- min over x < d of c(o - x) + g[r][x], and the same along
+// columns; one wave per line.  A lane's stores depend on the results of all
+// of its loads, and the wave issues every load of a line before any store.
+template <int D, bool ROWS>
+__device__ __forceinline__ void minplus_lines(double* g, const double* c1d, int d) {
+  constexpr int LG = D + 1;
+  constexpr int NQ = D >= 64 ? D / 64 : 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int line = wave; line < d; line += PNW) {
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = INFINITY;
+    for (int x = 0; x < d; ++x) {
+      const double gv = ROWS ? g[line * LG + x] : g[x * LG + line];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) acc[q] = fmin(acc[q], c1d[min(lane + 64 * q, D - 1) - x + D - 1] + gv);
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int o = lane + 64 * q;
+      if (o < d) {
+        if (ROWS) g[line * LG + o] = acc[q];
+        else g[o * LG + line] = acc[q];
+      }
+    }
+  }
+}
+
+// Lower bound <alpha^{c cbar}, a> + <alpha^c, b> for alpha = gamma log u
+// (u on supp(a) and u_Delta), both transforms over the whole ground space
+// (every grid cell and the diagonal bin).  The grid part of each transform is
+// separable: one min-plus pass along rows, one along columns.
+template <int D, int SPT>
+__device__ __forceinline__ double lower_bound(PairSmem<D>& s, const SupList<SPT>& ua, const SupList<SPT>& vb,
+                                              const Side& su, int d, double gamma, double aD, double bD,
+                                              const double* c1d, const double* cdd) {
+  constexpr int LG = D + 1;
+  constexpr double LN2 = 0.69314718055994530942;
+  static_assert(sizeof(double) * D * LG <= sizeof(float) * 2 * D * Cfg<D>::LDF, "grid in the FP32 operand pair");
+  double* g = reinterpret_cast<double*>(opXf<D>(s));
+  const int tid = threadIdx.x;
+  for (int c = tid; c < D * LG; c += PWGS) g[c] = INFINITY;
+  __syncthreads();
+  const double alD = su.mx > 0.0 ? gamma * (log(su.mx) + (double)su.ex * LN2) : -INFINITY;
+  double mD = -alD;   // alpha^c_Delta: the diagonal bin, then every cell of supp(a)
+  for (int k = 0; k < ua.nk(); ++k) {
+    const int c = ua.cell(k);
+    const float r = ua.res(k);
+    if (c >= 0 && r > 0.0f) {
+      const int i = c / D, j = c % D;
+      const double al = gamma * (log((double)r) + (double)(s.Pu[i] + s.Qu[j]) * LN2);
+      g[i * LG + j] = -al;
+      mD = fmin(mD, cdd[j - i + D - 1] - al);
+    }
+  }
+  const double acD = block_min<PNW>(mD, s.red);
+  minplus_lines<D, true>(g, c1d, d);
+  __syncthreads();
+  minplus_lines<D, false>(g, c1d, d);
+  __syncthreads();
+  // alpha^c on the grid (the diagonal bin as one more source), kept negated
+  // for the second transform; alpha^{c cbar}_Delta from it.
+  double mg = -acD;
+  for (int c = tid; c < d * d; c += PWGS) {
+    const int i = c / d, j = c % d;
+    const double cd = cdd[j - i + D - 1];
+    const double v = fmin(g[i * LG + j], cd - alD);
+    g[i * LG + j] = -v;
+    mg = fmin(mg, cd - v);
+  }
+  const double accD = block_min<PNW>(mg, s.red);
+  double sb = 0.0;
+  for (int k = 0; k < vb.nk(); ++k) {
+    const int c = vb.cell(k);
+    if (c >= 0) sb -= (double)vb.tgt(k) * g[(c / D) * LG + c % D];
+  }
+  sb = block_sum<PNW>(sb, s.red) + bD * acD;
+  minplus_lines<D, true>(g, c1d, d);
+  __syncthreads();
+  minplus_lines<D, false>(g, c1d, d);
+  __syncthreads();
+  double sa = 0.0;
+  for (int k = 0; k < ua.nk(); ++k) {
+    const int c = ua.cell(k);
+    if (c >= 0) {
+      const int i = c / D, j = c % D;
+      sa += (double)ua.tgt(k) * fmin(g[i * LG + j], cdd[j - i + D - 1] - acD);
+    }
+  }
+  sa = block_sum<PNW>(sa, s.red) + aD * accD;
+  __syncthreads();
+  return sa + sb;
+}
+
+// Upper bound <R, C> of Proposition 4: X = min(a / r(P), 1) scales u, then
+// Y = min(b / c(diag(X) P), 1) scales v, and the plan P'' of the scaled pair
+// plus the rank-one term e_r e_c^T / |e_c|_1 (e_r, e_c: the marginal
+// deficits of P'') is priced.  Every K application is an exact sum over the
+// supports; the residuals of ua and vb are left scaled.
+template <int D, int SPT>
+__device__ __forceinline__ double upper_bound(PairSmem<D>& s, SupList<SPT>& ua, SupList<SPT>& vb, const Side& su,
+                                              const Side& sv, ESum kv, int d, double aD, double bD,
+                                              const double* c1d, const double* cdd) {
+  constexpr int LDF = Cfg<D>::LDF;
+  static_assert(sizeof(float) * 2 * D * LDF + sizeof(double) * 4 * D <= sizeof(__bf16) * 4 * D * Cfg<D>::LDB,
+                "deficit grids and their sums in the operand buffers");
+  const int tid = threadIdx.x;
+  float* er = opXf<D>(s);                 // e_r on the grid, row stride LDF
+  float* ec = er + D * LDF;               // e_c
+  double* sums = reinterpret_cast<double*>(er + 2 * D * LDF);   // row, column sums of e_r; of e_c
+  for (int c = tid; c < 2 * D * LDF; c += PWGS) er[c] = 0.0f;
+  const int na = list_len(ua), nb = list_len(vb);
+  // 1. u' = X u with r(P) = u (K v)
+  sparse_kx<D, SPT, false>(s, ua, vb, s.Pv, s.Qv, d, na);
+  for (int k = 0; k < ua.nk(); ++k) {
+    const float r = ua.res(k);
+    if (ua.cell(k) >= 0 && r > 0.0f) {
+      const double rp = marg_at<D, SPT>(s, ua, k, r, s.Pu, s.Qu, sv.ex, sv.mx);
+      const double a = ua.tgt(k);
+      if (rp > a) ua.set_res(k, (float)((double)r * (a / rp)));
+    }
+  }
+  const double rD = ldxd(su.mx * kv.s, su.ex + kv.e);
+  const double uD = rD > aD ? su.mx * (aD / rD) : su.mx;   // u'_Delta = uD 2^su.ex
+  __syncthreads();
+  // 2. v' = Y v with c(P') = v (K^T u'); e_c = b - v' (K^T u')
+  sparse_kx<D, SPT, false>(s, vb, ua, s.Pu, s.Qu, d, nb);
+  ESum kuD{NEG, 0.0};
+  for (int k = 0; k < ua.nk(); ++k) {
+    const int c = ua.cell(k);
+    const float r = ua.res(k);
+    if (c >= 0 && r > 0.0f) {
+      const int i = c / D, j = c % D, dl = j - i + D - 1;
+      kuD = esum_add(kuD, ESum{s.Pu[i] + s.Qu[j] + s.tgde[dl], (double)r * (double)s.tgdm[dl]});
+    }
+  }
+  kuD = esum_add(block_esum<PNW>(kuD, s.rede, s.reds), ESum{su.ex, uD});   // (K^T u')_Delta
+  double ec1 = 0.0, eccd = 0.0;
+  for (int k = 0; k < vb.nk(); ++k) {
+    const int c = vb.cell(k);
+    if (c >= 0) {
+      const float r = vb.res(k);
+      const double b = vb.tgt(k);
+      double cp = 0.0;
+      if (r > 0.0f) {
+        cp = marg_at<D, SPT>(s, vb, k, r, s.Pv, s.Qv, su.ex, uD);
+        if (cp > b) {
+          const float rn = (float)((double)r * (b / cp));
+          vb.set_res(k, rn);
+          cp = rn > 0.0f ? marg_at<D, SPT>(s, vb, k, rn, s.Pv, s.Qv, su.ex, uD) : 0.0;
+        }
+      }
+      const double e = b - cp;
+      const int i = c / D, j = c % D;
+      ec[i * LDF + j] = (float)e;
+      ec1 += fabs(e);
+      eccd += e * cdd[j - i + D - 1];
+    }
+  }
+  const double cPD = ldxd(sv.mx * kuD.s, sv.ex + kuD.e);
+  const double vD = cPD > bD ? sv.mx * (bD / cPD) : sv.mx;   // v'_Delta = vD 2^sv.ex
+  const double ecD = bD - ldxd(vD * kuD.s, sv.ex + kuD.e);
+  __syncthreads();
+  // 3. e_r = a - u' (K v')
+  sparse_kx<D, SPT, false>(s, ua, vb, s.Pv, s.Qv, d, na);
+  ESum kvD{NEG, 0.0};
+  for (int k = 0; k < vb.nk(); ++k) {
+    const int c = vb.cell(k);
+    const float r = vb.res(k);
+    if (c >= 0 && r > 0.0f) {
+      const int i = c / D, j = c % D, dl = j - i + D - 1;
+      kvD = esum_add(kvD, ESum{s.Pv[i] + s.Qv[j] + s.tgde[dl], (double)r * (double)s.tgdm[dl]});
+    }
+  }
+  kvD = esum_add(block_esum<PNW>(kvD, s.rede, s.reds), ESum{sv.ex, vD});   // (K v')_Delta
+  double ercd = 0.0;
+  for (int k = 0; k < ua.nk(); ++k) {
+    const int c = ua.cell(k);
+    if (c >= 0) {
+      const float r = ua.res(k);
+      const double e = (double)ua.tgt(k) - (r > 0.0f ? marg_at<D, SPT>(s, ua, k, r, s.Pu, s.Qu, sv.ex, vD) : 0.0);
+      const int i = c / D, j = c % D;
+      er[i * LDF + j] = (float)e;
+      ercd += e * cdd[j - i + D - 1];
+    }
+  }
+  const double erD = aD - ldxd(uD * kvD.s, su.ex + kvD.e);
+  // 4. <P'', C>: grid to grid by (K o C) v', and the two diagonal-bin blocks
+  sparse_kx<D, SPT, true>(s, ua, vb, s.Pv, s.Qv, d, na);
+  double g = 0.0;
+  for (int k = 0; k < ua.nk(); ++k) {
+    const int c = ua.cell(k);
+    const float r = ua.res(k);
+    if (c >= 0 && r > 0.0f) {
+      const int i = c / D, j = c % D, dl = j - i + D - 1;
+      const int e0 = s.Pu[i] + s.Qu[j];
+      g += ldxd((double)r * (double)__int_as_float(ua.qe(k)), e0 + ua.q(k));
+      g += ldxd((double)r * vD * (double)s.tgdm[dl] * cdd[dl], e0 + sv.ex + s.tgde[dl]);
+    }
+  }
+  for (int k = 0; k < vb.nk(); ++k) {
+    const int c = vb.cell(k);
+    const float r = vb.res(k);
+    if (c >= 0 && r > 0.0f) {
+      const int i = c / D, j = c % D, dl = j - i + D - 1;
+      g += ldxd((double)r * uD * (double)s.tgdm[dl] * cdd[dl], s.Pv[i] + s.Qv[j] + su.ex + s.tgde[dl]);
+    }
+  }
+  // 5. the rank-one term: <e_r e_c^T, C> on the grid is separable into the
+  // row sums and the column sums of e_r and e_c
+  for (int x = tid; x < 4 * D; x += PWGS) {
+    const int which = x / D, o = x % D;
+    const float* G = which < 2 ? er : ec;
+    double acc = 0.0;
+    if (o < d) {
+      if (which & 1)
+        for (int i = 0; i < d; ++i) acc += (double)G[i * LDF + o];
+      else
+        for (int j = 0; j < d; ++j) acc += (double)G[o * LDF + j];
+    }
+    sums[x] = acc;
+  }
+  __syncthreads();
+  double tr = 0.0;
+  for (int x = tid; x < 2 * d * d; x += PWGS) {
+    const int h = x / (d * d), y = x % (d * d), i = y / d, k = y % d;
+    tr += sums[h * D + i] * c1d[i - k + D - 1] * sums[(2 + h) * D + k];
+  }
+  const double gs = block_sum<PNW>(g, s.red);
+  const double en = block_sum<PNW>(ec1, s.red) + fabs(ecD);
+  const double tt = block_sum<PNW>(tr, s.red) + ecD * block_sum<PNW>(ercd, s.red) + erD * block_sum<PNW>(eccd, s.red);
+  __syncthreads();
+  return gs + (en > 0.0 ? tt / en : 0.0);
+}
+
+// BOUNDS: also the error-control bounds (a kernel variant of its own, so
+// that the plain solve keeps its register allocation).
+template <int D, int SPT, bool BOUNDS>
 __device__ __forceinline__ void solve_pair(const PairParams& prm, PairSmem<D>& s, long long pair) {
   const int tid = threadIdx.x;
   const int d = prm.d;
@@ -1314,6 +1618,10 @@ __device__ __forceinline__ void solve_pair(const PairParams& prm, PairSmem<D>& s
       prm.iters[2 * pair + 1] = 0;
       prm.err[pair] = 0.0f;
       prm.status[pair] = 0;
+      if constexpr (BOUNDS) {
+        if (prm.upper) prm.upper[pair] = 0.0;
+        if (prm.lower) prm.lower[pair] = 0.0;
+      }
     }
     return;
   }
@@ -1505,6 +1813,26 @@ __device__ __forceinline__ void solve_pair(const PairParams& prm, PairSmem<D>& s
     }
   }
   const double cost = block_sum<PNW>(g, s.red);
+  if constexpr (BOUNDS) {
+    // needs a u from at least one iteration
+    double up = NAN, lo = NAN;
+    if (!bad && t > 0) {
+      double* c1d = reinterpret_cast<double*>(&s.fit[0][0][0]);
+      double* cdd = c1d + 2 * D;
+      for (int x = tid; x < 2 * D; x += PWGS) {
+        const double dl = fabs((double)(x - (D - 1)));
+        c1d[x] = pow(dl / d, prm.p);
+        cdd[x] = 2.0 * pow(dl / (2.0 * d), prm.p);
+      }
+      __syncthreads();
+      if (prm.lower) lo = lower_bound<D, SPT>(s, ua, vb, su, d, prm.gamma, aD, bD, c1d, cdd);
+      if (prm.upper) up = upper_bound<D, SPT>(s, ua, vb, su, sv, kv, d, aD, bD, c1d, cdd);
+    }
+    if (tid == 0) {
+      if (prm.upper) prm.upper[pair] = up;
+      if (prm.lower) prm.lower[pair] = lo;
+    }
+  }
   if (tid == 0) {
     int st = 0;
     if (!(err <= prm.tol)) st |= 1;
@@ -1520,17 +1848,17 @@ __device__ __forceinline__ void solve_pair(const PairParams& prm, PairSmem<D>& s
 
 // One workgroup per pair; the grid may be smaller than the batch (global-list
 // variant), in which case each workgroup takes pairs blockIdx.x, + gridDim.x, ...
-template <int D, int SPT>
+template <int D, int SPT, bool BOUNDS = false>
 __global__ __launch_bounds__(PWGS) void sinkhorn_pair_kernel(PairParams prm) {
   __shared__ PairSmem<D> s;
   if constexpr (SPT > 0 && D <= 128) {   // one pair per workgroup
     const long long pair = blockIdx.x;
     if (prm.only_redo && prm.redo[pair] != prm.only_redo) return;
-    solve_pair<D, SPT>(prm, s, pair);
+    solve_pair<D, SPT, BOUNDS>(prm, s, pair);
   } else {
     for (long long pair = blockIdx.x; pair < prm.n_pairs; pair += gridDim.x) {
       if (prm.only_redo && prm.redo[pair] != prm.only_redo) continue;
-      solve_pair<D, SPT>(prm, s, pair);
+      solve_pair<D, SPT, BOUNDS>(prm, s, pair);
       __syncthreads();
     }
   }

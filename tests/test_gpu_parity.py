@@ -12,7 +12,7 @@ import pytest
 import torch
 
 import pdgen
-from oracle import barycenter, ground, kmeans, sinkhorn
+from oracle import barycenter, bounds, ground, kmeans, matching, sinkhorn
 
 pytestmark = pytest.mark.gpu
 
@@ -214,6 +214,72 @@ def test_dense_centroid_same_schedule(pds, d):
         assert st[q] == 0 and float(r.err[q]) <= 1e-4, (q, st[q], float(r.err[q]))
         o = sinkhorn.sinkhorn(a, b, g, max_iter=int(iters[q].sum()), C=dense_C(d))
         assert rel(cost[q], o.cost) <= FP32_RTOL, (q, cost[q], o.cost)
+
+
+@pytest.mark.parametrize("d,g,tol,max_iter,n_small", [(32, 5e-3, 1e-4, 3000, 5), (64, 5e-3, 1e-3, 3000, 2),
+                                                      (32, 1e-2, 1e-4, 7, 5)])
+def test_bounds_match_oracle(pds, d, g, tol, max_iter, n_small):
+    """Error-control bounds of section 3 against the oracle's dense definitions
+    (rounded plan, c-transforms) at the same (u_t, v_t): upper within 1e-5
+    relative, lower within 1e-5 of the upper bound; both bracket the exact
+    transport value of the assignment problem.  Besides small pairs the batch
+    holds an empty diagram against a non-empty one, two empty diagrams, and a
+    diagram whose support exceeds the register lists at d = 64; the last case
+    stops every small pair at the iteration cap."""
+    rng = np.random.default_rng(21)
+    D1s, D2s = pdgen.pairs_batch(13, n_small, 5, 60)
+    b = rng.random(700)
+    big = np.stack([b, b + (1.0 - b) * rng.random(700)], 1).astype(np.float32)
+    empty = np.zeros((0, 2), np.float32)
+    D1s = list(D1s) + [empty, empty, big]
+    D2s = list(D2s) + [D2s[0], empty, D1s[1]]
+    n = len(D1s)
+    with pds.Context(d, g, tol=tol, max_iter=max_iter) as ctx:
+        dev = ctx.device
+        pts, off = pdgen.to_csr(D1s + D2s)
+        hist, mass, bad = pds.pd_discretize(ctx, torch.from_numpy(pts).to(dev), torch.from_numpy(off).to(dev))
+        ia = torch.arange(0, n, dtype=torch.int32, device=dev)
+        r = pds.sinkhorn_dist_batch(ctx, hist, hist, ia, ia + n, bounds=True)
+        plain = pds.sinkhorn_dist_batch(ctx, hist, hist, ia, ia + n)
+        torch.cuda.synchronize()
+    h = hist.cpu().numpy()
+    assert d != 64 or (h[n - 1] > 0).sum() > 512
+    up, lo = r.upper.cpu().numpy(), r.lower.cpu().numpy()
+    # the bounds variant leaves the solve itself unchanged
+    assert np.array_equal(r.cost.cpu().numpy(), plain.cost.cpu().numpy())
+    assert np.array_equal(r.iters.cpu().numpy(), plain.iters.cpu().numpy())
+    assert up[n - 2] == 0.0 and lo[n - 2] == 0.0
+    C = dense_C(d)
+    for q in list(range(n_small)) + [n - 3, n - 1]:
+        a_, b_ = ground.marginals(h[q], h[n + q])
+        o = sinkhorn.sinkhorn(h[q], h[n + q], g, max_iter=int(r.iters[q].sum()), C=C)
+        ou = bounds.upper_bound(o.log_u, o.log_v, a_, b_, C, g)
+        ol = bounds.lower_bound(o.log_u, a_, b_, C, g)
+        assert rel(up[q], ou) <= FP32_RTOL, (q, up[q], ou)
+        assert abs(lo[q] - ol) <= FP32_RTOL * abs(ou), (q, lo[q], ol)
+        if q < n_small:
+            exact = matching.ot_assignment(matching.hist_points(h[q], d), matching.hist_points(h[n + q], d))
+            assert lo[q] <= exact * (1 + 1e-6) + 1e-9 and exact <= up[q] * (1 + 1e-6), (q, lo[q], exact, up[q])
+    if max_iter < 100:
+        assert np.all(r.status.cpu().numpy()[:n_small] & 1)
+
+
+def test_bounds_grid_beyond_128(pds):
+    """Bounds at d = 136 (grids beyond 128 run on global operand slices):
+    finite, ordered, and the upper bound close to the converged cost."""
+    d, g = 136, 2e-3
+    D1s, D2s = pdgen.pairs_batch(17, 3, 20, 120)
+    with pds.Context(d, g, tol=1e-4, max_iter=3000) as ctx:
+        dev = ctx.device
+        pts, off = pdgen.to_csr(list(D1s) + list(D2s))
+        hist, mass, bad = pds.pd_discretize(ctx, torch.from_numpy(pts).to(dev), torch.from_numpy(off).to(dev))
+        ia = torch.arange(0, 3, dtype=torch.int32, device=dev)
+        r = pds.sinkhorn_dist_batch(ctx, hist, hist, ia, ia + 3, bounds=True)
+        torch.cuda.synchronize()
+    up, lo, cost = r.upper.cpu().numpy(), r.lower.cpu().numpy(), r.cost.cpu().numpy()
+    assert np.all(r.status.cpu().numpy() == 0)
+    assert np.all(np.isfinite(up)) and np.all(np.isfinite(lo)) and np.all(lo <= up)
+    assert np.all(np.abs(up - cost) <= 0.01 * cost), (up, cost)
 
 
 def test_alone_equals_in_batch(pds):
