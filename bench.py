@@ -150,15 +150,19 @@ def pmc_probe(pts_d, off_d, switch_tol: float, copy_mib: int = 256):
     print(json.dumps({"pmc_probe": True, "copy_bytes": copy_mib << 20, "pairs": n}))
 
 
+# The translation unit of the plain pair kernel and what it includes (the
+# bounds variant and the log-domain path are compiled in units of their own).
+PAIR_KERNEL_SOURCES = ("pdsink_api.hip", "pdsink_device.h", "sinkhorn_log.h", "sinkhorn_pair.h")
+
+
 def source_hash() -> str:
-    """Hash of the kernel sources: counter figures apply only to the build they were taken on."""
+    """Hash of the pair kernel's sources: counter figures apply only to the build they were taken on."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1805_08331_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".h", ".hip")):
-            with open(os.path.join(csrc, name), "rb") as fh:
-                h.update(name.encode() + b"\0" + fh.read())
+    for name in PAIR_KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
 
 

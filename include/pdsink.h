@@ -51,6 +51,8 @@ extern "C" {
 #define PDSINK_ST_MAX_ITER   1  /* stopped at max_iter with err > tol              */
 #define PDSINK_ST_NONFINITE  2  /* a kernel product vanished or overflowed: cost = NaN */
 #define PDSINK_ST_RANGE      4  /* scaling residual left the representable range  */
+#define PDSINK_ST_LOG_PATH   8  /* solved again in the log domain after NONFINITE or
+                                 * RANGE (then those two bits are clear)          */
 
 typedef struct pdsink_ctx pdsink_ctx;
 
@@ -121,7 +123,11 @@ int pd_discretize(pdsink_ctx* ctx, const float* pts, const int64_t* offsets, int
  * Masses are the histogram sums.  n_pairs = 0 is a no-op.  Any support size
  * is accepted: pairs whose supports exceed the register lists (512 cells per
  * side) run again with their lists in the workspace, from the same launch
- * sequence. */
+ * sequence.  A pair whose scaled solve ends NONFINITE or RANGE (a kernel so
+ * sharp that one grid step costs tens of octaves, gamma d^2 well below 1) is
+ * solved again from the start by the same iteration in FP64 log-sum-exp form
+ * over the two supports (up to 1024 cells per side; larger pairs keep their
+ * flags): status PDSINK_ST_LOG_PATH, iterations reported in the FP32 slot. */
 int sinkhorn_dist_batch(pdsink_ctx* ctx, int64_t n_pairs,
                         const float* hist_a, const float* hist_b,
                         const int32_t* ia, const int32_t* ib,
@@ -138,7 +144,8 @@ int sinkhorn_dist_batch(pdsink_ctx* ctx, int64_t n_pairs,
  *         the ground space, every grid cell and the diagonal bin) computed
  *         by separable min-plus passes over the grid
  * so that lower <= L_C(a, b) <= upper up to rounding.  Both are NaN for a pair
- * whose status has PDSINK_ST_NONFINITE, and 0 for an empty pair.  The K
+ * whose status has PDSINK_ST_NONFINITE or PDSINK_ST_LOG_PATH, and 0 for an
+ * empty pair.  The K
  * applications inside are exact sums over the two supports, O(|supp a| |supp b|)
  * per pair; the transforms cost O(d^3) per pair.  Other arguments, errors and
  * the workspace are those of sinkhorn_dist_batch. */

@@ -45,6 +45,7 @@ PDSINK_BF16_REFINE = 1
 PDSINK_ST_MAX_ITER = 1
 PDSINK_ST_NONFINITE = 2
 PDSINK_ST_RANGE = 4
+PDSINK_ST_LOG_PATH = 8
 
 PDSINK_OP_DIST = 0
 PDSINK_OP_KMEANS = 1

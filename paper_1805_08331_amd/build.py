@@ -2,8 +2,8 @@
 
 ``python -m paper_1805_08331_amd.build`` (or ``build()``) compiles
 ``csrc/pdsink_api.hip`` (the C ABI and the plain kernels) and
-``csrc/pdsink_bounds.hip`` (the kernel variant with the error-control bounds),
-both of which include the kernel headers, into
+``csrc/pdsink_bounds.hip`` (the kernel variant with the error-control bounds)
+and ``csrc/pdsink_log.hip`` (the log-domain path for flagged pairs) into
 ``paper_1805_08331_amd/libpdsink.so``.  It always recompiles.
 """
 from __future__ import annotations
@@ -15,7 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdsink.so")
-SOURCES = ["pdsink_api.hip", "pdsink_bounds.hip"]
+SOURCES = ["pdsink_api.hip", "pdsink_bounds.hip", "pdsink_log.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -11,6 +11,7 @@
 
 #include "../../include/pdsink.h"
 #include "pdsink_device.h"
+#include "sinkhorn_log.h"
 #include "sinkhorn_pair.h"
 
 using namespace pdsink;
@@ -201,12 +202,35 @@ int run_pairs(const pdsink_ctx* ctx, int64_t n_pairs, const float* ha, const flo
   pp.lower = ex.lower;
   pp.gamma = ctx->prm.gamma;
   pp.p = ctx->prm.p;
+  int rc;
   switch (ctx->D) {
-    case 32: return launch_levels<32>(pp, ex.n_slots, st);
-    case 64: return launch_levels<64>(pp, ex.n_slots, st);
-    case 128: return launch_levels<128>(pp, ex.n_slots, st);
-    default: return launch_levels<256>(pp, ex.n_slots, st);
+    case 32: rc = launch_levels<32>(pp, ex.n_slots, st); break;
+    case 64: rc = launch_levels<64>(pp, ex.n_slots, st); break;
+    case 128: rc = launch_levels<128>(pp, ex.n_slots, st); break;
+    default: rc = launch_levels<256>(pp, ex.n_slots, st); break;
   }
+  if (rc || ex.state || ex.gout) return rc;
+  // Pairs flagged NONFINITE or RANGE are solved again in the log domain (same
+  // stream, no host synchronisation; a launch that only reads the flags when
+  // none is).  Not for the barycenter solves, which need the scaled form of v.
+  LogParams lp;
+  lp.d = ctx->prm.d;
+  lp.p = ctx->prm.p;
+  lp.gamma = ctx->prm.gamma;
+  lp.tol = ctx->prm.tol;
+  lp.max_iter = ctx->prm.max_iter;
+  lp.hist_a = ha;
+  lp.hist_b = hb;
+  lp.ia = ia;
+  lp.ib = ib;
+  lp.n_pairs = n_pairs;
+  lp.cost = cost;
+  lp.iters = iters;
+  lp.err = err;
+  lp.status = status;
+  lp.upper = ex.upper;
+  lp.lower = ex.lower;
+  return launch_log_path(lp, ex.n_slots, st) ? PDSINK_EDEVICE : PDSINK_OK;
 }
 
 // pair q = (diagram q / k, centroid q % k)

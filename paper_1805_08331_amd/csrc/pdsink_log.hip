@@ -1,0 +1,245 @@
+// Log-domain Sinkhorn for the pairs that the scaled solve flags.
+//
+// The scaled solve keeps u and v as 2^(P_i + Q_j) times an FP32 residual.
+// When the kernel is so sharp that one grid step costs tens of octaves
+// (gamma d^2 well below 1), the scalings stop being close to a row times
+// column product and the residual leaves its range (status RANGE, or a
+// vanished product, NONFINITE).  This path reruns such a pair from the start
+// with the same iteration (alternating updates from v = 1, u first, the
+// marginal error of section 3 checked before every u-update, Proposition 3's
+// cost) written with log-sum-exp in FP64 over the two supports:
+//   log u_c = log a_c - LSE_e(log v_e - C_ce / gamma)   (e over supp(b) and Delta)
+// and likewise for v, with C_ce = c(i - k) + c(j - l) on the grid and
+// c_Delta on the diagonal bin.  The first u-update sees v = 1 on every grid
+// cell, whose sum factors over the two axes.  Work per iteration is
+// O(|supp a| |supp b|) exponentials.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "pdsink_device.h"
+#include "sinkhorn_log.h"
+
+namespace pdsink {
+
+namespace {
+
+constexpr int LWG = 512;
+constexpr int LNW = LWG / 64;
+
+struct LogSmem {
+  int cell[2][LOG_CAP];     // support cells i * d + j; side 0: a (u), side 1: b (v)
+  double lt[2][LOG_CAP];    // log targets
+  double ls[2][LOG_CAP];    // log scalings
+  double lk[2][LOG_CAP];    // log of the latest K application at each cell
+  double c1d[512];          // c(delta) = (|delta| / d)^p, index delta + d - 1
+  double cdd[512];          // c_Delta by delta = j - i, index delta + d - 1
+  double red[LNW];
+  int cnt[LWG];
+  int n[2];
+};
+
+__device__ __forceinline__ double block_max_d(double v, double* red) { return -block_min<LNW>(-v, red); }
+
+// log(exp(x) + exp(y)) for x, y that may be -inf.
+__device__ __forceinline__ double lse2(double x, double y) {
+  const double m = fmax(x, y);
+  if (m == -INFINITY) return -INFINITY;
+  return m + log(exp(x - m) + exp(y - m));
+}
+
+// Support list of one histogram, in cell order: counts per thread chunk, a
+// serial scan of the 512 counts, then each thread writes its chunk.  Returns
+// false (and leaves the list empty) when the support exceeds LOG_CAP.
+__device__ bool build_list(LogSmem& S, int side, const float* __restrict__ h, int d) {
+  const int n = d * d, per = (n + LWG - 1) / LWG;
+  const int c0 = min((int)threadIdx.x * per, n), c1 = min(c0 + per, n);
+  int k = 0;
+  for (int c = c0; c < c1; ++c) k += h[c] > 0.0f;
+  S.cnt[threadIdx.x] = k;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int t = 0; t < LWG; ++t) {
+      const int v = S.cnt[t];
+      S.cnt[t] = acc;
+      acc += v;
+    }
+    S.n[side] = acc;
+  }
+  __syncthreads();
+  const int total = S.n[side];
+  if (total > LOG_CAP) return false;
+  int off = S.cnt[threadIdx.x];
+  for (int c = c0; c < c1; ++c) {
+    const float v = h[c];
+    if (v > 0.0f) {
+      S.cell[side][off] = c;
+      S.lt[side][off] = log((double)v);
+      ++off;
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
+// LSE over the sources of side `src` (plus the diagonal-bin source xD) of
+// ls - C / gamma at grid cell (i, j).
+__device__ __forceinline__ double lse_at(const LogSmem& S, int src, int i, int j, int d, double xD, double ig) {
+  const int n = S.n[src];
+  double m = xD;
+  for (int e = 0; e < n; ++e) {
+    const int c = S.cell[src][e], k = c / d, l = c % d;
+    m = fmax(m, S.ls[src][e] - (S.c1d[i - k + d - 1] + S.c1d[j - l + d - 1]) * ig);
+  }
+  if (m == -INFINITY) return -INFINITY;
+  double s = exp(xD - m);
+  for (int e = 0; e < n; ++e) {
+    const int c = S.cell[src][e], k = c / d, l = c % d;
+    s += exp(S.ls[src][e] - (S.c1d[i - k + d - 1] + S.c1d[j - l + d - 1]) * ig - m);
+  }
+  return m + log(s);
+}
+
+// LSE over the sources of side `src` plus xD of ls - c_Delta / gamma: the
+// K application at the diagonal bin (C_Delta,Delta = 0).
+__device__ double lse_delta(LogSmem& S, int src, int d, double xD, double ig) {
+  const int n = S.n[src];
+  double m = -INFINITY;
+  for (int e = threadIdx.x; e < n; e += LWG) {
+    const int c = S.cell[src][e], i = c / d, j = c % d;
+    m = fmax(m, S.ls[src][e] - S.cdd[j - i + d - 1] * ig);
+  }
+  m = fmax(block_max_d(m, S.red), xD);
+  if (m == -INFINITY) return -INFINITY;
+  double s = 0.0;
+  for (int e = threadIdx.x; e < n; e += LWG) {
+    const int c = S.cell[src][e], i = c / d, j = c % d;
+    s += exp(S.ls[src][e] - S.cdd[j - i + d - 1] * ig - m);
+  }
+  s = block_sum<LNW>(s, S.red) + exp(xD - m);
+  return m + log(s);
+}
+
+__device__ void solve_log_pair(const LogParams& prm, LogSmem& S, long long pair) {
+  const int d = prm.d, tid = threadIdx.x;
+  const double ig = 1.0 / prm.gamma;
+  const float* A = prm.hist_a + (size_t)prm.ia[pair] * d * d;
+  const float* B = prm.hist_b + (size_t)prm.ib[pair] * d * d;
+  for (int x = tid; x < 2 * d - 1; x += LWG) {
+    const double dl = fabs((double)(x - (d - 1)));
+    S.c1d[x] = pow(dl / d, prm.p);
+    S.cdd[x] = 2.0 * pow(dl / (2.0 * d), prm.p);
+  }
+  if (!build_list(S, 0, A, d) || !build_list(S, 1, B, d)) return;   // stays flagged
+  double ma = 0.0, mb = 0.0;
+  for (int e = tid; e < S.n[0]; e += LWG) ma += exp(S.lt[0][e]);
+  for (int e = tid; e < S.n[1]; e += LWG) mb += exp(S.lt[1][e]);
+  ma = block_sum<LNW>(ma, S.red);
+  mb = block_sum<LNW>(mb, S.red);
+  const double aD = mb, bD = ma, m = ma + mb;
+  const double ltD0 = log(aD), ltD1 = log(bD);
+  // First u-update against v = 1 on the whole grid and on Delta:
+  // (K 1)_ij = r_i r_j + k_Delta(i, j), r_i = sum_k exp(-c(i - k) / gamma);
+  // (K 1)_Delta = sum over the grid of k_Delta + 1.  log r_i goes to lk[1].
+  for (int i = tid; i < d; i += LWG) {
+    double mx = -INFINITY;
+    for (int k = 0; k < d; ++k) mx = fmax(mx, -S.c1d[i - k + d - 1] * ig);
+    double s = 0.0;
+    for (int k = 0; k < d; ++k) s += exp(-S.c1d[i - k + d - 1] * ig - mx);
+    S.lk[1][i] = mx + log(s);
+  }
+  __syncthreads();
+  for (int e = tid; e < S.n[0]; e += LWG) {
+    const int c = S.cell[0][e], i = c / d, j = c % d;
+    S.lk[0][e] = lse2(S.lk[1][i] + S.lk[1][j], -S.cdd[j - i + d - 1] * ig);
+  }
+  double mxD = 0.0;   // the Delta source (C = 0)
+  for (int c = tid; c < d * d; c += LWG) mxD = fmax(mxD, -S.cdd[c % d - c / d + d - 1] * ig);
+  mxD = block_max_d(mxD, S.red);
+  double sD = 0.0;
+  for (int c = tid; c < d * d; c += LWG) sD += exp(-S.cdd[c % d - c / d + d - 1] * ig - mxD);
+  sD = block_sum<LNW>(sD, S.red) + exp(-mxD);
+  double lkD0 = mxD + log(sD);
+  double luD = -INFINITY, lvD = 0.0;
+  int t = 0;
+  double err = INFINITY;
+  for (;;) {
+    if (t >= 1) {
+      double e1 = 0.0;
+      for (int e = tid; e < S.n[0]; e += LWG) e1 += fabs(exp(S.ls[0][e] + S.lk[0][e]) - exp(S.lt[0][e]));
+      e1 = block_sum<LNW>(e1, S.red) + fabs(exp(luD + lkD0) - aD);
+      err = e1 / m;
+      if (err <= prm.tol || t >= prm.max_iter) break;
+    }
+    // u-update
+    for (int e = tid; e < S.n[0]; e += LWG) S.ls[0][e] = S.lt[0][e] - S.lk[0][e];
+    luD = ltD0 - lkD0;
+    __syncthreads();
+    // v-update: v = b / K^T u
+    for (int e = tid; e < S.n[1]; e += LWG) {
+      const int c = S.cell[1][e], i = c / d, j = c % d;
+      S.lk[1][e] = lse_at(S, 0, i, j, d, luD - S.cdd[j - i + d - 1] * ig, ig);
+    }
+    const double lkD1 = lse_delta(S, 0, d, luD, ig);
+    for (int e = tid; e < S.n[1]; e += LWG) S.ls[1][e] = S.lt[1][e] - S.lk[1][e];
+    lvD = ltD1 - lkD1;
+    __syncthreads();
+    ++t;
+    // K v for the next check and u-update
+    for (int e = tid; e < S.n[0]; e += LWG) {
+      const int c = S.cell[0][e], i = c / d, j = c % d;
+      S.lk[0][e] = lse_at(S, 1, i, j, d, lvD - S.cdd[j - i + d - 1] * ig, ig);
+    }
+    lkD0 = lse_delta(S, 1, d, lvD, ig);
+  }
+  // Proposition 3's value <P_t, C> summed over the supports and the Delta blocks.
+  double g = 0.0;
+  for (int e = tid; e < S.n[0]; e += LWG) {
+    const int c = S.cell[0][e], i = c / d, j = c % d;
+    const double lu = S.ls[0][e];
+    for (int f = 0; f < S.n[1]; ++f) {
+      const int c2 = S.cell[1][f], k = c2 / d, l = c2 % d;
+      const double C = S.c1d[i - k + d - 1] + S.c1d[j - l + d - 1];
+      g += exp(lu + S.ls[1][f] - C * ig) * C;
+    }
+    const double cd = S.cdd[j - i + d - 1];
+    g += exp(lu + lvD - cd * ig) * cd;
+  }
+  for (int f = tid; f < S.n[1]; f += LWG) {
+    const int c = S.cell[1][f], i = c / d, j = c % d;
+    const double cd = S.cdd[j - i + d - 1];
+    g += exp(luD + S.ls[1][f] - cd * ig) * cd;
+  }
+  const double cost = block_sum<LNW>(g, S.red);
+  if (tid == 0) {
+    int st = ST_LOG;
+    if (!(err <= prm.tol)) st |= 1;
+    if (!isfinite(cost)) st |= 2;
+    prm.cost[pair] = cost;
+    prm.iters[2 * pair] = 0;
+    prm.iters[2 * pair + 1] = t;
+    prm.err[pair] = (float)err;
+    prm.status[pair] = st;
+    if (prm.upper) prm.upper[pair] = NAN;
+    if (prm.lower) prm.lower[pair] = NAN;
+  }
+}
+
+__global__ __launch_bounds__(LWG) void sinkhorn_log_kernel(LogParams prm) {
+  __shared__ LogSmem S;
+  for (long long pair = blockIdx.x; pair < prm.n_pairs; pair += gridDim.x) {
+    if (!(prm.status[pair] & 6)) continue;   // NONFINITE or RANGE
+    solve_log_pair(prm, S, pair);
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+int launch_log_path(const LogParams& lp, int n_slots, hipStream_t st) {
+  hipLaunchKernelGGL(sinkhorn_log_kernel, dim3((unsigned)n_slots), dim3(LWG), 0, st, lp);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace pdsink

@@ -282,6 +282,59 @@ def test_bounds_grid_beyond_128(pds):
     assert np.all(np.abs(up - cost) <= 0.01 * cost), (up, cost)
 
 
+def _log_oracle_cost(h1, h2, g, iters, C):
+    """Oracle cost after exactly ``iters`` iterations, log-sum-exp form on the
+    rows of supp(a) (in range at any gamma)."""
+    a, b = ground.marginals(h1, h2)
+    sa = a > 0
+    cost, t, _, _, _ = sinkhorn.solve_log(a[sa], b, C[sa, :], g, tol=0.0, max_iter=iters)
+    assert t == iters
+    return cost
+
+
+@pytest.mark.parametrize("d,g,max_iter,log_path", [(32, 2e-5, 1500, True), (32, 1e-4, 1500, None),
+                                                   (64, 5e-5, 800, None)])
+def test_tiny_gamma_same_schedule(pds, d, g, max_iter, log_path):
+    """Kernels far sharper than the paper's (gamma d^2 from 0.02 to 0.2: one
+    grid step costs 10 to 70 octaves).  Where the scaled form's range gives
+    out, the pair is solved again in the FP64 log domain (status LOG_PATH)
+    and matches the log-sum-exp oracle to 1e-9; where it holds, the FP32 path
+    matches to 1e-5.  Same iteration counts on both sides."""
+    D1s, D2s = pdgen.pairs_batch(31, 3, 10, 60)
+    C = dense_C(d)
+    with pds.Context(d, g, tol=0.0, max_iter=max_iter) as ctx:
+        cost, iters, err, st, hist = run_pairs(pds, ctx, D1s, D2s)
+    n = len(D1s)
+    logp = (st & pds._lib.PDSINK_ST_LOG_PATH) != 0
+    if log_path is not None:
+        assert np.all(logp == log_path), st
+    if d == 64:   # this batch has pairs on both paths
+        assert logp.any() and not logp.all(), st
+    assert np.all((st & 6) == 0), st
+    for q in range(n):
+        it = int(iters[q].sum())
+        assert it == max_iter
+        ref = _log_oracle_cost(hist[q], hist[n + q], g, it, C)
+        assert rel(cost[q], ref) <= (1e-9 if logp[q] else FP32_RTOL), (q, st[q], cost[q], ref)
+
+
+def test_log_path_bounds_are_nan(pds):
+    """Bounds are not computed for a pair solved by the log-domain path."""
+    d, g = 32, 2e-5
+    D1s, D2s = pdgen.pairs_batch(31, 2, 10, 60)
+    with pds.Context(d, g, tol=1e-4, max_iter=300) as ctx:
+        dev = ctx.device
+        pts, off = pdgen.to_csr(list(D1s) + list(D2s))
+        hist, mass, bad = pds.pd_discretize(ctx, torch.from_numpy(pts).to(dev), torch.from_numpy(off).to(dev))
+        ia = torch.arange(0, 2, dtype=torch.int32, device=dev)
+        r = pds.sinkhorn_dist_batch(ctx, hist, hist, ia, ia + 2, bounds=True)
+        torch.cuda.synchronize()
+    st = r.status.cpu().numpy()
+    assert np.all(st & pds._lib.PDSINK_ST_LOG_PATH), st
+    assert np.all(np.isnan(r.upper.cpu().numpy())) and np.all(np.isnan(r.lower.cpu().numpy()))
+    assert np.all(np.isfinite(r.cost.cpu().numpy()))
+
+
 def test_alone_equals_in_batch(pds):
     """A pair's result does not depend on the batch it runs in (bitwise)."""
     d, g = 64, 2e-3
