@@ -43,11 +43,12 @@ def flops_of(iters_total: int, n_pairs: int, d: int = D) -> float:
     return 8.0 * d ** 3 * iters_total + 12.0 * d ** 3 * n_pairs
 
 
-def run_gpu(precision: str, steps: int, warmup: int, pts_d, off_d, switch_tol: float):
+def run_gpu(precision: str, steps: int, warmup: int, pts_d, off_d, switch_tol: float, gamma: float = GAMMA,
+            max_iter: int = 5000):
     import torch
     import paper_1805_08331_amd as pds
 
-    ctx = pds.Context(D, GAMMA, tol=TOL, max_iter=5000, precision=precision, switch_tol=switch_tol)
+    ctx = pds.Context(D, gamma, tol=TOL, max_iter=max_iter, precision=precision, switch_tol=switch_tol)
     dev = ctx.device
     n = NPAIRS
     hist = torch.empty((2 * n, D, D), dtype=torch.float32, device=dev)
@@ -67,7 +68,7 @@ def run_gpu(precision: str, steps: int, warmup: int, pts_d, off_d, switch_tol: f
         pds.pd_discretize(ctx, pts_d, off_d, hist, mass, nbad)
         if i is not None:
             ev[i][0].record(stream)
-        pds.sinkhorn_dist_batch(ctx, hist, hist, ia, ib, out=out, ws=ws)
+        pds.sinkhorn_dist_batch(ctx, hist, hist, ia, ib, out=out, ws=ws, check_indices=False)
         if i is not None:
             ev[i][1].record(stream)
 
@@ -99,6 +100,9 @@ def run_gpu(precision: str, steps: int, warmup: int, pts_d, off_d, switch_tol: f
         "n_bad_status": int((status != 0).sum()),
         "max_err": float(err.max()),
         "iters_per_pair": iters.sum(axis=1),
+        "status": status,
+        "iters_q": {"p50": int(np.percentile(iters.sum(axis=1), 50)),
+                    "p99": int(np.percentile(iters.sum(axis=1), 99))},
     }
 
 
@@ -224,6 +228,24 @@ def write_traffic(fetch_csv: str, write_csv: str):
     print(json.dumps(rec))
 
 
+def gamma_sweep(pts_d, off_d, switch_tol: float):
+    """The benchmark batch at gamma_n = 0.1 / n, n = 1 ... 5000 (down to 2e-5):
+    iterations, throughput and the paths the pairs took, one JSON line per
+    (gamma, precision)."""
+    for n in (1, 10, 100, 1000, 2000, 5000):
+        g = 0.1 / n
+        for prec in ("bf16", "fp32"):
+            r = run_gpu(prec, 1, 1, pts_d, off_d, switch_tol, gamma=g, max_iter=40000)
+            st = r["status"]
+            print(json.dumps({
+                "gamma": g, "gamma_d2": g * D * D, "precision": prec, "pairs": NPAIRS,
+                "pair_iters": r["iters_total"], "kernel_ms": float(np.mean(r["kernel_ms"])),
+                "pair_it_per_s": r["iters_total"] / (float(np.mean(r["kernel_ms"])) / 1e3),
+                "iters_p50": r["iters_q"]["p50"], "iters_p99": r["iters_q"]["p99"],
+                "converged": int((st == 0).sum()), "log_path": int(((st & 8) != 0).sum()),
+                "flagged": int(((st & 6) != 0).sum()), "max_iter": int(((st & 1) != 0).sum())}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -235,6 +257,8 @@ def main():
                     help="run one BF16 batch and a 256 MiB device copy (for counter runs), then exit")
     ap.add_argument("--switch-tol", type=float, default=1.1e-3,
                     help="BF16 -> FP32 switch point of the marginal error (1.1 x tol)")
+    ap.add_argument("--gamma-sweep", action="store_true",
+                    help="run the batch at gamma = 0.1 / n down to 2e-5 and print one line per gamma, then exit")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic record from two --pmc-probe counter runs, then exit")
     args = ap.parse_args()
@@ -256,6 +280,9 @@ def main():
 
     if args.pmc_probe:
         pmc_probe(pts_d, off_d, args.switch_tol)
+        return
+    if args.gamma_sweep:
+        gamma_sweep(pts_d, off_d, args.switch_tol)
         return
 
     res = {}
