@@ -229,12 +229,12 @@ def write_traffic(fetch_csv: str, write_csv: str):
 
 
 def gamma_sweep(pts_d, off_d, switch_tol: float):
-    """The benchmark batch at gamma_n = 0.1 / n, n = 1 ... 5000 (down to 2e-5):
-    iterations, throughput and the paths the pairs took, one JSON line per
-    (gamma, precision)."""
-    for n in (1, 10, 100, 1000, 2000, 5000):
+    """The benchmark batch (BF16 + refinement) at gamma_n = 0.1 / n, n = 1 ... 5000
+    (down to 2e-5): iterations, throughput and the paths the pairs took, one
+    JSON line per gamma."""
+    for n in (1, 10, 100, 200, 500, 1000, 2000, 5000):
         g = 0.1 / n
-        for prec in ("bf16", "fp32"):
+        for prec in ("bf16",):
             r = run_gpu(prec, 1, 1, pts_d, off_d, switch_tol, gamma=g, max_iter=40000)
             st = r["status"]
             print(json.dumps({

@@ -1157,7 +1157,7 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, bool w
     }
   }
   if (flags & 1) bad = 1;
-  if (flags & 2) range = 1;
+  if (flags & 2) range |= 2;   // more suspects than the lists hold
 
   // Column extrema of sweep 0 (against the row centres of sweep 0), then the
   // rows and columns of sweep 1.
@@ -1246,7 +1246,7 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, bool w
   }
   dot = tot;
   mres_out = mr + 1;
-  if (mres_out > 100) range = 1;
+  if (mres_out > 100) range |= 1;
   if (late_x) {   // switch of the X format: every read of the K x buffer is done now
     zero_x<D>(s, out_bf16);
     __syncthreads();
@@ -1695,6 +1695,7 @@ __device__ __forceinline__ void solve_pair(const PairParams& prm, PairSmem<D>& s
                      v_dense || x_lp != lp_now, t >= 1, err, stop, dotu, su.mres, bad, range, errD, m, prm.tol,
                      prm.switch_tol, lowp, t, prm.max_iter);
     if (stop || bad) break;
+    if (SPT == 1 && (range & 2)) break;
     x_lp = lp_now;
     su.ex = -kv.e;
     su.mx = aD / kv.s;
@@ -1719,6 +1720,13 @@ __device__ __forceinline__ void solve_pair(const PairParams& prm, PairSmem<D>& s
     if (lp_now) ++it_lp;
     else ++it_hp;
     if (bad) break;
+    if (SPT == 1 && (range & 2)) break;
+  }
+  if (SPT == 1 && (range & 2)) {
+    // The LDS suspect list overflowed: the global-list variant, whose
+    // suspect arrays hold every cell, solves the pair again from the start.
+    if (tid == 0) prm.redo[pair] = (unsigned char)(prm.only_redo + 1);
+    return;
   }
 
   // Transport cost of Proposition 3 for (u_t, v_t), FP32 contractions and FP64 sums:
