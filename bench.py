@@ -255,8 +255,8 @@ def main():
     ap.add_argument("--only", choices=["bf16", "fp32"], default=None, help="run one precision only")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="run one BF16 batch and a 256 MiB device copy (for counter runs), then exit")
-    ap.add_argument("--switch-tol", type=float, default=1.1e-3,
-                    help="BF16 -> FP32 switch point of the marginal error (1.1 x tol)")
+    ap.add_argument("--switch-tol", type=float, default=0.8e-3,
+                    help="BF16 -> FP32 switch point of the marginal error (0.8 x tol: the shortest batch time)")
     ap.add_argument("--gamma-sweep", action="store_true",
                     help="run the batch at gamma = 0.1 / n down to 2e-5 and print one line per gamma, then exit")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
