@@ -19,9 +19,10 @@ def header_functions():
     return sorted(set(n for n in names if n not in ("if", "while")))
 
 
-def test_header_declares_the_four_operations():
+def test_header_declares_the_operations():
     names = header_functions()
-    for op in ("pd_discretize", "sinkhorn_dist_batch", "pd_barycenter", "kmeans_assign"):
+    for op in ("pd_discretize", "sinkhorn_dist_batch", "sinkhorn_dist_bounds_batch", "pd_barycenter",
+               "kmeans_assign", "kmeans_lloyd"):
         assert op in names
     assert "pdsink_ctx_create" in names and "pdsink_strerror" in names
 
@@ -71,6 +72,8 @@ def test_strerror_and_host_side_validation():
     assert lib.pdsink_workspace_bytes(None, 0, 10, ctypes.byref(n)) == _lib.PDSINK_EINVAL
     assert lib.sinkhorn_dist_batch(None, 1, None, None, None, None, None, None, None, None, None, 0,
                                    None) == _lib.PDSINK_EINVAL
+    assert lib.sinkhorn_dist_bounds_batch(None, 1, None, None, None, None, None, None, None, None, None, None,
+                                          None, 0, None) == _lib.PDSINK_EINVAL
     assert lib.pd_discretize(None, None, None, 1, None, None, None, None) == _lib.PDSINK_EINVAL
     assert lib.kmeans_assign(None, 1, None, 1, None, None, None, None, None, 0, None) == _lib.PDSINK_EINVAL
     e, o = ctypes.c_double(), ctypes.c_int32()
