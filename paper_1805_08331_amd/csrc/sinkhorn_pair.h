@@ -346,32 +346,38 @@ __device__ __forceinline__ void build_kernels_bf16(PairSmem<D>& s, const int* P,
   // are skipped; chunks of columns k >= d hold exact zeros (P_k = NEG) and
   // are written without table reads.
   const int nch = (d + 15) / 16;          // 16-entry chunks per row that touch k < d
-  // item = ((side * nch + chunk) * d + row): adjacent lanes take adjacent rows
-  // of one chunk, so their table reads hit adjacent LDS banks.
-  for (int item = threadIdx.x; item < 2 * nch * d; item += PWGS) {
-    const int i = item % d, sc = item / d;
-    const bool first = sc < nch;
-    const int k0 = 16 * (first ? sc : sc - nch);
-    const int* X = (first ? P : Q) + k0;
-    const int base = 126 - (first ? s.R : s.S)[i];
+  // item = chunk * d + row: adjacent lanes take adjacent rows of one chunk, so
+  // their table reads hit adjacent LDS banks; both kernels of the row share
+  // the 16 table words (kt1 with P and R, kt2 with Q and S).
+  for (int item = threadIdx.x; item < nch * d; item += PWGS) {
+    const int i = item % d, k0 = 16 * (item / d);
     const int* tw = s.tkb + i - k0 + D - 1;    // tw[-t] = word of delta = i - (k0 + t)
-    const int4 xa = *reinterpret_cast<const int4*>(X), xb = *reinterpret_cast<const int4*>(X + 4);
-    const int4 xc = *reinterpret_cast<const int4*>(X + 8), xd = *reinterpret_cast<const int4*>(X + 12);
-    const int xs[16] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w, xc.x, xc.y, xc.z, xc.w, xd.x, xd.y, xd.z, xd.w};
-    unsigned int pk[8];
+    int wd[16];
 #pragma unroll
-    for (int t = 0; t < 16; t += 2) {
-      const int s0 = min(max(xs[t] + base, -(1 << 20)), 1 << 20);
-      const int s1 = min(max(xs[t + 1] + base, -(1 << 20)), 1 << 20);
-      // below the smallest normal the clamp leaves 0 or a BF16 subnormal
-      // pattern (< 2^-126): either is negligible against the row maximum
-      const int v0 = min(max(tw[-t] + (s0 << 7), 0), 0x7FFF);
-      const int v1 = min(max(tw[-t - 1] + (s1 << 7), 0), 0x7FFF);
-      pk[t >> 1] = (unsigned)v0 | ((unsigned)v1 << 16);
+    for (int t = 0; t < 16; ++t) wd[t] = tw[-t];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int* X = (side == 0 ? P : Q) + k0;
+      const int base = 126 - (side == 0 ? s.R : s.S)[i];
+      const int4 xa = *reinterpret_cast<const int4*>(X), xb = *reinterpret_cast<const int4*>(X + 4);
+      const int4 xc = *reinterpret_cast<const int4*>(X + 8), xd = *reinterpret_cast<const int4*>(X + 12);
+      const int xs[16] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w,
+                          xc.x, xc.y, xc.z, xc.w, xd.x, xd.y, xd.z, xd.w};
+      unsigned int pk[8];
+#pragma unroll
+      for (int t = 0; t < 16; t += 2) {
+        const int s0 = min(max(xs[t] + base, -(1 << 20)), 1 << 20);
+        const int s1 = min(max(xs[t + 1] + base, -(1 << 20)), 1 << 20);
+        // below the smallest normal the clamp leaves 0 or a BF16 subnormal
+        // pattern (< 2^-126): either is negligible against the row maximum
+        const int v0 = min(max(wd[t] + (s0 << 7), 0), 0x7FFF);
+        const int v1 = min(max(wd[t + 1] + (s1 << 7), 0), 0x7FFF);
+        pk[t >> 1] = (unsigned)v0 | ((unsigned)v1 << 16);
+      }
+      uint4* dst = reinterpret_cast<uint4*>((side == 0 ? opK1b<D>(s) : opK2b<D>(s)) + i * LDB + k0);
+      dst[0] = uint4{pk[0], pk[1], pk[2], pk[3]};
+      dst[1] = uint4{pk[4], pk[5], pk[6], pk[7]};
     }
-    uint4* dst = reinterpret_cast<uint4*>((first ? opK1b<D>(s) : opK2b<D>(s)) + i * LDB + k0);
-    dst[0] = uint4{pk[0], pk[1], pk[2], pk[3]};
-    dst[1] = uint4{pk[4], pk[5], pk[6], pk[7]};
   }
   const int nz = D / 16 - nch;            // all-zero chunks per row
   for (int item = threadIdx.x; item < 2 * nz * d; item += PWGS) {
