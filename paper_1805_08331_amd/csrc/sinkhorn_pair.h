@@ -161,6 +161,10 @@ struct PairSmem : OpsLds<D> {
   alignas(16) int Pv[D];
   alignas(16) int Qv[D];
   int R[D], S[D];
+  // BF16 kernel build: the input scales clamped to +-2^20 and shifted to the
+  // exponent field of a BF16 word
+  alignas(16) int P7[D];
+  alignas(16) int Q7[D];
   // refit extrema: [sweep][row max, row min, column max, column min][D]
   alignas(16) int fit[2][4][D];   // also the FP64 cost tables of the bounds
   int sflag;               // bit 0: a suspect's exact value vanished
@@ -357,21 +361,21 @@ __device__ __forceinline__ void build_kernels_bf16(PairSmem<D>& s, const int* P,
     for (int t = 0; t < 16; ++t) wd[t] = tw[-t];
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
-      const int* X = (side == 0 ? P : Q) + k0;
-      const int base = 126 - (side == 0 ? s.R : s.S)[i];
-      const int4 xa = *reinterpret_cast<const int4*>(X), xb = *reinterpret_cast<const int4*>(X + 4);
-      const int4 xc = *reinterpret_cast<const int4*>(X + 8), xd = *reinterpret_cast<const int4*>(X + 12);
+      // word = table word + ((X_k - R_i + 126) << 7), clamped to [0, 0x7FFF]:
+      // below the smallest normal the clamp leaves 0 or a BF16 subnormal
+      // pattern (< 2^-126), either negligible against the row maximum.  X_k
+      // is clamped to +-2^20 beforehand (X7), so that no sum overflows.
+      const int* X7 = (side == 0 ? s.P7 : s.Q7) + k0;
+      const int base7 = (126 - (side == 0 ? s.R : s.S)[i]) << 7;
+      const int4 xa = *reinterpret_cast<const int4*>(X7), xb = *reinterpret_cast<const int4*>(X7 + 4);
+      const int4 xc = *reinterpret_cast<const int4*>(X7 + 8), xd = *reinterpret_cast<const int4*>(X7 + 12);
       const int xs[16] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w,
                           xc.x, xc.y, xc.z, xc.w, xd.x, xd.y, xd.z, xd.w};
       unsigned int pk[8];
 #pragma unroll
       for (int t = 0; t < 16; t += 2) {
-        const int s0 = min(max(xs[t] + base, -(1 << 20)), 1 << 20);
-        const int s1 = min(max(xs[t + 1] + base, -(1 << 20)), 1 << 20);
-        // below the smallest normal the clamp leaves 0 or a BF16 subnormal
-        // pattern (< 2^-126): either is negligible against the row maximum
-        const int v0 = min(max(wd[t] + (s0 << 7), 0), 0x7FFF);
-        const int v1 = min(max(wd[t + 1] + (s1 << 7), 0), 0x7FFF);
+        const int v0 = min(max(wd[t] + xs[t] + base7, 0), 0x7FFF);
+        const int v1 = min(max(wd[t + 1] + xs[t + 1] + base7, 0), 0x7FFF);
         pk[t >> 1] = (unsigned)v0 | ((unsigned)v1 << 16);
       }
       uint4* dst = reinterpret_cast<uint4*>((side == 0 ? opK1b<D>(s) : opK2b<D>(s)) + i * LDB + k0);
@@ -660,6 +664,12 @@ __device__ __forceinline__ float* apply_K(PairSmem<D>& s, const int* P, const in
                                           bool trim, bool tri) {
   prep_update<D>(s);
   compute_RS<D>(s, P, Q, d, H);
+  if (lowp) {
+    for (int r = threadIdx.x; r < D; r += PWGS) {
+      s.P7[r] = min(max(P[r], -(1 << 20)), 1 << 20) << 7;
+      s.Q7[r] = min(max(Q[r], -(1 << 20)), 1 << 20) << 7;
+    }
+  }
   __syncthreads();
   float* Wb = wbuf<D>(s, lowp);
   if (lowp) {
