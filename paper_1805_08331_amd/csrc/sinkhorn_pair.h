@@ -448,6 +448,47 @@ __device__ __forceinline__ void gemm_xk(PairSmem<D>& s, const int* Q, bool trim)
   constexpr int LDF = Cfg<D>::LDF, LDB = Cfg<D>::LDB;
   const int lane = threadIdx.x & 63, lr = lane & 31, lk = lane >> 5;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave index, held in a scalar register
+  if constexpr (BF16 && Cfg<D>::NT == 4) {
+    // The wave's two tiles share the column block tj, hence the kt2 operand:
+    // one chain alone while only the upper tile's l range is live, then both
+    // chains from one read of kt2 (each accumulator sees the same sequence of
+    // steps as when the tiles run one after the other).
+    int tk0, tk1, tj;
+    xk_tile<D>(w, 0, tk0, tj);
+    xk_tile<D>(w, 1, tk1, tj);
+    const int j = tj * 32 + lr;
+    const int lb0 = trim ? tk0 * 32 : 0, lb1 = trim ? tk1 * 32 : 0;
+    const __bf16* xa0 = s.u.b.X + (tk0 * 32 + lr) * LDB + 8 * lk;
+    const __bf16* xa1 = s.u.b.X + (tk1 * 32 + lr) * LDB + 8 * lk;
+    const __bf16* kb = s.u.b.K2 + j * LDB + 8 * lk;
+    floatx16 acc0 = {}, acc1 = {};
+#pragma unroll 2
+    for (int l0 = lb0; l0 < lb1; l0 += 16) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(xa0 + l0);
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(kb + l0);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc0, 0, 0, 0);
+    }
+#pragma unroll 2
+    for (int l0 = lb1; l0 < D; l0 += 16) {
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(kb + l0);
+      const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(xa0 + l0);
+      const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(xa1 + l0);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b, acc1, 0, 0, 0);
+    }
+    mfma_drain();
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bf16x4 v0 = {(__bf16)acc0[4 * q], (__bf16)acc0[4 * q + 1], (__bf16)acc0[4 * q + 2],
+                         (__bf16)acc0[4 * q + 3]};
+      *reinterpret_cast<bf16x4*>(s.u.b.Tt + j * LDB + tk0 * 32 + 8 * q + 4 * lk) = v0;
+      const bf16x4 v1 = {(__bf16)acc1[4 * q], (__bf16)acc1[4 * q + 1], (__bf16)acc1[4 * q + 2],
+                         (__bf16)acc1[4 * q + 3]};
+      *reinterpret_cast<bf16x4*>(s.u.b.Tt + j * LDB + tk1 * 32 + 8 * q + 4 * lk) = v1;
+    }
+    return;
+  }
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     int tk, tj;
