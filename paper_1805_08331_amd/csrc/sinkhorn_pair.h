@@ -541,6 +541,61 @@ __device__ __forceinline__ void gemm_kt(PairSmem<D>& s, const int* P, float* Wb,
   constexpr int LDF = Cfg<D>::LDF, LDB = Cfg<D>::LDB;
   const int lane = threadIdx.x & 63, lr = lane & 31, lk = lane >> 5;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave index, held in a scalar register
+  if constexpr (BF16 && Cfg<D>::NT == 4) {
+    if (tri) {
+      // The 10 upper tiles: waves 0-3 take two tiles of one row block, which
+      // share the kt1 operand, (0,0)+(0,1), (0,2)+(0,3), (1,1)+(1,2),
+      // (2,2)+(2,3); waves 4 and 5 take (1,3) and (3,3), each as two
+      // accumulation chains over the halves of k; waves 6 and 7 rest.
+      floatx16 acc0 = {}, acc1 = {};
+      int ti = 0, tj = 0;
+      if (w < 4) {
+        ti = w < 2 ? 0 : w - 1;
+        tj = w == 0 ? 0 : (w == 2 ? 1 : 2);
+        const __bf16* ka = s.u.b.K1 + (ti * 32 + lr) * LDB + 8 * lk;
+        const __bf16* t0 = s.u.b.Tt + (tj * 32 + lr) * LDB + 8 * lk;
+        const __bf16* t1 = t0 + 32 * LDB;
+#pragma unroll 2
+        for (int k0 = 0; k0 < D; k0 += 16) {
+          const bf16x8 a = *reinterpret_cast<const bf16x8*>(ka + k0);
+          const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(t0 + k0);
+          const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(t1 + k0);
+          acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
+        }
+        mfma_drain();
+      } else if (w < 6) {
+        ti = w == 4 ? 1 : 3;
+        tj = 3;
+        const __bf16* ka = s.u.b.K1 + (ti * 32 + lr) * LDB + 8 * lk;
+        const __bf16* ta = s.u.b.Tt + (tj * 32 + lr) * LDB + 8 * lk;
+#pragma unroll 2
+        for (int k0 = 0; k0 < D / 2; k0 += 16) {
+          const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(ka + k0);
+          const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(ta + k0);
+          const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(ka + k0 + D / 2);
+          const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(ta + k0 + D / 2);
+          acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc1, 0, 0, 0);
+        }
+        mfma_drain();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc0[r] += acc1[r];
+      }
+      __syncthreads();
+      if (w < 6) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) Wb[(ti * 32 + 8 * (r >> 2) + 4 * lk + (r & 3)) * LDF + tj * 32 + lr] = acc0[r];
+      }
+      if (w < 4) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          Wb[(ti * 32 + 8 * (r >> 2) + 4 * lk + (r & 3)) * LDF + (tj + 1) * 32 + lr] = acc1[r];
+      }
+      __syncthreads();
+      return;
+    }
+  }
   int ti0, tj0, ti1, tj1;
   const bool has0 = kt_tile<D>(w, 0, tri, ti0, tj0);
   const bool two = has0 && kt_tile<D>(w, 1, tri, ti1, tj1);
