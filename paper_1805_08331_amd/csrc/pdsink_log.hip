@@ -28,10 +28,17 @@ namespace {
 constexpr int LWG = 512;
 constexpr int LNW = LWG / 64;
 
+// One support entry as a source of the log-sum-exps: its log scaling and its
+// cell (i << 16) | j, read with one 16-byte load.
+struct alignas(16) Src {
+  double ls;
+  int cell;
+  int pad;
+};
+
 struct LogSmem {
-  int cell[2][LOG_CAP];     // support cells (i << 16) | j; side 0: a (u), side 1: b (v)
+  Src src[2][LOG_CAP];      // side 0: a (u), side 1: b (v)
   double lt[2][LOG_CAP];    // log targets
-  double ls[2][LOG_CAP];    // log scalings
   double lk[2][LOG_CAP];    // log of the latest K application at each cell
   double c1d[512];          // c(delta) = (|delta| / d)^p, index delta + d - 1
   double cdd[512];          // c_Delta by delta = j - i, index delta + d - 1
@@ -85,7 +92,7 @@ __device__ bool build_list(LogSmem& S, int side, const float* __restrict__ h, in
   for (int c = c0; c < c1; ++c) {
     const float v = h[c];
     if (v > 0.0f) {
-      S.cell[side][off] = ((c / d) << 16) | (c % d);
+      S.src[side][off].cell = ((c / d) << 16) | (c % d);
       S.lt[side][off] = log((double)v);
       ++off;
     }
@@ -95,37 +102,45 @@ __device__ bool build_list(LogSmem& S, int side, const float* __restrict__ h, in
 }
 
 // LSE over the sources of side `src` (plus the diagonal-bin source xD) of
-// ls - C / gamma at grid cell (i, j); four sources per step.
+// ls - C / gamma at grid cell (i, j); four sources per step.  P2: the ground
+// exponent is 2, so C = ((i - k)^2 + (j - l)^2) / d^2 without table reads.
+template <bool P2>
 __device__ __forceinline__ double lse_at(const LogSmem& S, int src, int i, int j, int d, double xD, double ig) {
-  const int n = S.n[src];
-  const int* cl = S.cell[src];
-  const double* ls = S.ls[src];
+  const int ns = S.n[src];
+  const Src* sr = S.src[src];
   const double* ci = S.c1d + i + d - 1;   // ci[-k] = c(i - k)
   const double* cj = S.c1d + j + d - 1;
+  const double igd = ig / ((double)d * (double)d);
   auto x_of = [&](int e) {
-    const int c = cl[e];
-    return ls[e] - (ci[-(c >> 16)] + cj[-(c & 0xFFFF)]) * ig;
+    const Src q = sr[e];
+    const int k = q.cell >> 16, l = q.cell & 0xFFFF;
+    if constexpr (P2) {
+      const int di = i - k, dj = j - l;
+      return q.ls - (double)(di * di + dj * dj) * igd;
+    } else {
+      return q.ls - (ci[-k] + cj[-l]) * ig;
+    }
   };
   double m0 = xD, m1 = -INFINITY, m2 = -INFINITY, m3 = -INFINITY;
   int e = 0;
-  for (; e + 4 <= n; e += 4) {
+  for (; e + 4 <= ns; e += 4) {
     m0 = fmax(m0, x_of(e));
     m1 = fmax(m1, x_of(e + 1));
     m2 = fmax(m2, x_of(e + 2));
     m3 = fmax(m3, x_of(e + 3));
   }
-  for (; e < n; ++e) m0 = fmax(m0, x_of(e));
+  for (; e < ns; ++e) m0 = fmax(m0, x_of(e));
   const double m = fmax(fmax(m0, m1), fmax(m2, m3));
   if (m == -INFINITY) return -INFINITY;
   double s0 = exp_neg(xD - m), s1 = 0.0, s2 = 0.0, s3 = 0.0;
   e = 0;
-  for (; e + 4 <= n; e += 4) {
+  for (; e + 4 <= ns; e += 4) {
     s0 += exp_neg(x_of(e) - m);
     s1 += exp_neg(x_of(e + 1) - m);
     s2 += exp_neg(x_of(e + 2) - m);
     s3 += exp_neg(x_of(e + 3) - m);
   }
-  for (; e < n; ++e) s0 += exp_neg(x_of(e) - m);
+  for (; e < ns; ++e) s0 += exp_neg(x_of(e) - m);
   return m + log((s0 + s1) + (s2 + s3));
 }
 
@@ -135,15 +150,15 @@ __device__ double lse_delta(LogSmem& S, int src, int d, double xD, double ig) {
   const int n = S.n[src];
   double m = -INFINITY;
   for (int e = threadIdx.x; e < n; e += LWG) {
-    const int c = S.cell[src][e], i = c >> 16, j = c & 0xFFFF;
-    m = fmax(m, S.ls[src][e] - S.cdd[j - i + d - 1] * ig);
+    const int c = S.src[src][e].cell, i = c >> 16, j = c & 0xFFFF;
+    m = fmax(m, S.src[src][e].ls - S.cdd[j - i + d - 1] * ig);
   }
   m = fmax(block_max_d(m, S.red), xD);
   if (m == -INFINITY) return -INFINITY;
   double s = 0.0;
   for (int e = threadIdx.x; e < n; e += LWG) {
-    const int c = S.cell[src][e], i = c >> 16, j = c & 0xFFFF;
-    s += exp_neg(S.ls[src][e] - S.cdd[j - i + d - 1] * ig - m);
+    const int c = S.src[src][e].cell, i = c >> 16, j = c & 0xFFFF;
+    s += exp_neg(S.src[src][e].ls - S.cdd[j - i + d - 1] * ig - m);
   }
   s = block_sum<LNW>(s, S.red) + exp_neg(xD - m);
   return m + log(s);
@@ -152,6 +167,7 @@ __device__ double lse_delta(LogSmem& S, int src, int d, double xD, double ig) {
 __device__ void solve_log_pair(const LogParams& prm, LogSmem& S, long long pair) {
   const int d = prm.d, tid = threadIdx.x;
   const double ig = 1.0 / prm.gamma;
+  const bool p2 = prm.p == 2.0;
   const float* A = prm.hist_a + (size_t)prm.ia[pair] * d * d;
   const float* B = prm.hist_b + (size_t)prm.ib[pair] * d * d;
   for (int x = tid; x < 2 * d - 1; x += LWG) {
@@ -179,7 +195,7 @@ __device__ void solve_log_pair(const LogParams& prm, LogSmem& S, long long pair)
   }
   __syncthreads();
   for (int e = tid; e < S.n[0]; e += LWG) {
-    const int c = S.cell[0][e], i = c >> 16, j = c & 0xFFFF;
+    const int c = S.src[0][e].cell, i = c >> 16, j = c & 0xFFFF;
     S.lk[0][e] = lse2(S.lk[1][i] + S.lk[1][j], -S.cdd[j - i + d - 1] * ig);
   }
   double mxD = 0.0;   // the Delta source (C = 0)
@@ -195,49 +211,51 @@ __device__ void solve_log_pair(const LogParams& prm, LogSmem& S, long long pair)
   for (;;) {
     if (t >= 1) {
       double e1 = 0.0;
-      for (int e = tid; e < S.n[0]; e += LWG) e1 += fabs(exp(S.ls[0][e] + S.lk[0][e]) - exp(S.lt[0][e]));
+      for (int e = tid; e < S.n[0]; e += LWG) e1 += fabs(exp(S.src[0][e].ls + S.lk[0][e]) - exp(S.lt[0][e]));
       e1 = block_sum<LNW>(e1, S.red) + fabs(exp(luD + lkD0) - aD);
       err = e1 / m;
       if (err <= prm.tol || t >= prm.max_iter) break;
     }
     // u-update
-    for (int e = tid; e < S.n[0]; e += LWG) S.ls[0][e] = S.lt[0][e] - S.lk[0][e];
+    for (int e = tid; e < S.n[0]; e += LWG) S.src[0][e].ls = S.lt[0][e] - S.lk[0][e];
     luD = ltD0 - lkD0;
     __syncthreads();
     // v-update: v = b / K^T u
     for (int e = tid; e < S.n[1]; e += LWG) {
-      const int c = S.cell[1][e], i = c >> 16, j = c & 0xFFFF;
-      S.lk[1][e] = lse_at(S, 0, i, j, d, luD - S.cdd[j - i + d - 1] * ig, ig);
+      const int c = S.src[1][e].cell, i = c >> 16, j = c & 0xFFFF;
+      S.lk[1][e] = p2 ? lse_at<true>(S, 0, i, j, d, luD - S.cdd[j - i + d - 1] * ig, ig)
+                      : lse_at<false>(S, 0, i, j, d, luD - S.cdd[j - i + d - 1] * ig, ig);
     }
     const double lkD1 = lse_delta(S, 0, d, luD, ig);
-    for (int e = tid; e < S.n[1]; e += LWG) S.ls[1][e] = S.lt[1][e] - S.lk[1][e];
+    for (int e = tid; e < S.n[1]; e += LWG) S.src[1][e].ls = S.lt[1][e] - S.lk[1][e];
     lvD = ltD1 - lkD1;
     __syncthreads();
     ++t;
     // K v for the next check and u-update
     for (int e = tid; e < S.n[0]; e += LWG) {
-      const int c = S.cell[0][e], i = c >> 16, j = c & 0xFFFF;
-      S.lk[0][e] = lse_at(S, 1, i, j, d, lvD - S.cdd[j - i + d - 1] * ig, ig);
+      const int c = S.src[0][e].cell, i = c >> 16, j = c & 0xFFFF;
+      S.lk[0][e] = p2 ? lse_at<true>(S, 1, i, j, d, lvD - S.cdd[j - i + d - 1] * ig, ig)
+                      : lse_at<false>(S, 1, i, j, d, lvD - S.cdd[j - i + d - 1] * ig, ig);
     }
     lkD0 = lse_delta(S, 1, d, lvD, ig);
   }
   // Proposition 3's value <P_t, C> summed over the supports and the Delta blocks.
   double g = 0.0;
   for (int e = tid; e < S.n[0]; e += LWG) {
-    const int c = S.cell[0][e], i = c >> 16, j = c & 0xFFFF;
-    const double lu = S.ls[0][e];
+    const int c = S.src[0][e].cell, i = c >> 16, j = c & 0xFFFF;
+    const double lu = S.src[0][e].ls;
     for (int f = 0; f < S.n[1]; ++f) {
-      const int c2 = S.cell[1][f], k = c2 >> 16, l = c2 & 0xFFFF;
+      const int c2 = S.src[1][f].cell, k = c2 >> 16, l = c2 & 0xFFFF;
       const double C = S.c1d[i - k + d - 1] + S.c1d[j - l + d - 1];
-      g += exp(lu + S.ls[1][f] - C * ig) * C;
+      g += exp(lu + S.src[1][f].ls - C * ig) * C;
     }
     const double cd = S.cdd[j - i + d - 1];
     g += exp(lu + lvD - cd * ig) * cd;
   }
   for (int f = tid; f < S.n[1]; f += LWG) {
-    const int c = S.cell[1][f], i = c >> 16, j = c & 0xFFFF;
+    const int c = S.src[1][f].cell, i = c >> 16, j = c & 0xFFFF;
     const double cd = S.cdd[j - i + d - 1];
-    g += exp(luD + S.ls[1][f] - cd * ig) * cd;
+    g += exp(luD + S.src[1][f].ls - cd * ig) * cd;
   }
   const double cost = block_sum<LNW>(g, S.red);
   if (tid == 0) {
