@@ -120,6 +120,72 @@ __global__ __launch_bounds__(WG) void discretize_kernel(const float* __restrict_
   if (threadIdx.x == 0) mass[n] = kept;
 }
 
+// Launch order of the pairs.  The batch runs one workgroup per pair (one per
+// compute unit at a time), so its length is set by the solves that start
+// last; the iteration count of a pair is largest when one of its diagrams is
+// small (much of its mass goes to the diagonal), so pairs are launched by
+// increasing min(|supp a|, |supp b|), counted on the device and bucketed
+// (ORDER_BINS buckets; the order within a bucket is arbitrary and does not
+// affect any result).
+constexpr int ORDER_BINS = 1024;
+size_t order_bytes(int64_t n) { return align256((size_t)n * 4) * 2 + align256((size_t)ORDER_BINS * 4); }
+
+__global__ void order_zero_kernel(int* bins) {
+  for (int b = threadIdx.x; b < ORDER_BINS; b += blockDim.x) bins[b] = 0;
+}
+
+__global__ __launch_bounds__(WG) void order_key_kernel(const float* __restrict__ ha, const float* __restrict__ hb,
+                                                       const int32_t* ia, const int32_t* ib, int d, int shift,
+                                                       int* key, int* bins) {
+  __shared__ int ra[NWAVE], rb[NWAVE];
+  const long long q = blockIdx.x;
+  const float* A = ha + (size_t)ia[q] * d * d;
+  const float* B = hb + (size_t)ib[q] * d * d;
+  int ca = 0, cb = 0;
+  for (int c = threadIdx.x; c < d * d; c += WG) {
+    ca += A[c] > 0.0f;
+    cb += B[c] > 0.0f;
+  }
+  ca = wave_sum(ca);
+  cb = wave_sum(cb);
+  if ((threadIdx.x & 63) == 0) {
+    ra[threadIdx.x >> 6] = ca;
+    rb[threadIdx.x >> 6] = cb;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ta = 0, tb = 0;
+    for (int w = 0; w < NWAVE; ++w) {
+      ta += ra[w];
+      tb += rb[w];
+    }
+    const int k = min(min(ta, tb) >> shift, ORDER_BINS - 1);
+    key[q] = k;
+    atomicAdd(&bins[k], 1);
+  }
+}
+
+// Exclusive scan of the bucket counts (one workgroup of ORDER_BINS threads).
+__global__ __launch_bounds__(ORDER_BINS) void order_scan_kernel(int* bins) {
+  __shared__ int t[ORDER_BINS];
+  const int b = threadIdx.x;
+  const int v = bins[b];
+  t[b] = v;
+  __syncthreads();
+  for (int off = 1; off < ORDER_BINS; off <<= 1) {
+    const int add = b >= off ? t[b - off] : 0;
+    __syncthreads();
+    t[b] += add;
+    __syncthreads();
+  }
+  bins[b] = t[b] - v;
+}
+
+__global__ __launch_bounds__(WG) void order_scatter_kernel(const int* key, int* bins, int* perm, long long n) {
+  const long long q = (long long)blockIdx.x * WG + threadIdx.x;
+  if (q < n) perm[atomicAdd(&bins[key[q]], 1)] = (int)q;
+}
+
 // Optional per-pair buffers of a distance launch.
 struct PairExtras {
   char* lists = nullptr;      // global support lists, list_bytes(D) per workgroup slot
@@ -130,6 +196,7 @@ struct PairExtras {
   double* gout = nullptr;     // [n_pairs][d * d] gradient terms
   double* upper = nullptr;    // [n_pairs] error-control bounds
   double* lower = nullptr;
+  char* order = nullptr;      // order_bytes(n_pairs): keys, permutation, buckets
 };
 
 size_t list_bytes(int D) { return align256((size_t)52 * D * D); }   // 2 sides x 5 arrays + 3 suspect arrays, x D^2 x 4 bytes
@@ -202,6 +269,23 @@ int run_pairs(const pdsink_ctx* ctx, int64_t n_pairs, const float* ha, const flo
   pp.lower = ex.lower;
   pp.gamma = ctx->prm.gamma;
   pp.p = ctx->prm.p;
+  pp.perm = nullptr;
+  if (ex.order && n_pairs > ctx->n_cu) {
+    int* key = reinterpret_cast<int*>(ex.order);
+    int* perm = reinterpret_cast<int*>(ex.order + align256((size_t)n_pairs * 4));
+    int* bins = reinterpret_cast<int*>(ex.order + 2 * align256((size_t)n_pairs * 4));
+    const int d = ctx->prm.d;
+    int shift = 0;
+    while (((d * d) >> shift) >= ORDER_BINS) ++shift;
+    hipLaunchKernelGGL(order_zero_kernel, dim3(1), dim3(WG), 0, st, bins);
+    hipLaunchKernelGGL(order_key_kernel, dim3((unsigned)n_pairs), dim3(WG), 0, st, ha, hb, ia, ib, d, shift, key, bins);
+    hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(ORDER_BINS), 0, st, bins);
+    hipLaunchKernelGGL(order_scatter_kernel, dim3((unsigned)((n_pairs + WG - 1) / WG)), dim3(WG), 0, st, key, bins, perm,
+                       (long long)n_pairs);
+    const int rc = last_error();
+    if (rc) return rc;
+    pp.perm = perm;
+  }
   int rc;
   switch (ctx->D) {
     case 32: rc = launch_levels<32>(pp, ex.n_slots, st); break;
@@ -414,12 +498,12 @@ int pdsink_ctx_params(const pdsink_ctx* ctx, pdsink_params* out) {
 int pdsink_workspace_bytes(const pdsink_ctx* ctx, int op, int64_t n_items, size_t* bytes) {
   if (!ctx || !bytes || n_items < 0) return PDSINK_EINVAL;
   switch (op) {
-    case PDSINK_OP_DIST:   // routing flag per pair, support lists per slot
-      *bytes = align256(n_items) + slots_for(ctx, n_items) * slot_bytes(ctx->D);
+    case PDSINK_OP_DIST:   // routing flag per pair, support lists per slot, launch order
+      *bytes = align256(n_items) + slots_for(ctx, n_items) * slot_bytes(ctx->D) + order_bytes(n_items);
       return PDSINK_OK;
-    case PDSINK_OP_KMEANS:   // ia, ib, cost, iters, err, status, redo per pair, lists per slot
+    case PDSINK_OP_KMEANS:   // ia, ib, cost, iters, err, status, redo per pair, lists per slot, launch order
       *bytes = align256(n_items * 4) * 2 + align256(n_items * 8) + align256(n_items * 8) + align256(n_items * 4) * 2 +
-               align256(n_items) + slots_for(ctx, n_items) * slot_bytes(ctx->D);
+               align256(n_items) + slots_for(ctx, n_items) * slot_bytes(ctx->D) + order_bytes(n_items);
       return PDSINK_OK;
     case PDSINK_OP_BARYCENTER:   // the KMEANS arrays for n pairs, warm states, gradient terms
       *bytes = align256(n_items * 4) * 2 + align256(n_items * 8) + align256(n_items * 8) + align256(n_items * 4) * 2 +
@@ -471,6 +555,7 @@ int sinkhorn_dist_bounds_batch(pdsink_ctx* ctx, int64_t n_pairs, const float* hi
   ex.n_slots = (int)slots_for(ctx, n_pairs);
   ex.lists = (char*)ws + align256(n_pairs);
   ex.ops = ex.lists + ex.n_slots * list_bytes(ctx->D);
+  ex.order = ex.lists + ex.n_slots * slot_bytes(ctx->D);
   ex.upper = upper;
   ex.lower = lower;
   return run_pairs(ctx, n_pairs, hist_a, hist_b, ia, ib, cost, iters, err, status, (unsigned char*)ws, ex,
@@ -508,6 +593,7 @@ int kmeans_assign(pdsink_ctx* ctx, int64_t n_diag, const float* hist, int32_t k,
   ex.lists = w;
   ex.n_slots = (int)slots_for(ctx, np);
   ex.ops = w + ex.n_slots * list_bytes(ctx->D);
+  ex.order = w + ex.n_slots * slot_bytes(ctx->D);
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(kmeans_pairs_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, n_diag, k, ia, ib);
   int rc = last_error();

@@ -97,6 +97,9 @@ struct PairParams {
   double* lower;
   double gamma;
   double p;
+  // optional launch order of the register-list launch: workgroup b solves
+  // pair perm[b] (NULL: pair b)
+  const int* perm;
 };
 
 constexpr int PWGS = 512;      // threads per pair workgroup
@@ -1972,11 +1975,12 @@ template <int D, int SPT, bool BOUNDS = false>
 __global__ __launch_bounds__(PWGS) void sinkhorn_pair_kernel(PairParams prm) {
   __shared__ PairSmem<D> s;
   if constexpr (SPT > 0 && D <= 128) {   // one pair per workgroup
-    const long long pair = blockIdx.x;
+    const long long pair = prm.perm ? prm.perm[blockIdx.x] : blockIdx.x;
     if (prm.only_redo && prm.redo[pair] != prm.only_redo) return;
     solve_pair<D, SPT, BOUNDS>(prm, s, pair);
   } else {
-    for (long long pair = blockIdx.x; pair < prm.n_pairs; pair += gridDim.x) {
+    for (long long idx = blockIdx.x; idx < prm.n_pairs; idx += gridDim.x) {
+      const long long pair = (SPT > 0 && prm.perm) ? prm.perm[idx] : idx;
       if (prm.only_redo && prm.redo[pair] != prm.only_redo) continue;
       solve_pair<D, SPT, BOUNDS>(prm, s, pair);
       __syncthreads();
