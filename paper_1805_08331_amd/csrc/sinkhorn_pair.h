@@ -157,7 +157,8 @@ struct GlobalOps {
 
 template <int D>
 struct PairSmem : OpsLds<D> {
-  int tge[2 * D], tgde[2 * D], tkb[2 * D];
+  alignas(16) int tge[2 * D];
+  int tgde[2 * D], tkb[2 * D];
   float tgm[2 * D], tgdm[2 * D], tc1[2 * D], tcd[2 * D];
   alignas(16) int Pu[D];
   alignas(16) int Qu[D];
@@ -301,21 +302,52 @@ __device__ __forceinline__ void compute_RS(PairSmem<D>& s, const int* P, const i
   const int i0 = 4 * (rows ? combo : combo - NRB / 2);
   const int* X = rows ? P : Q;
   const int k0 = part * KPT;
-  const int* tw = s.tge + i0 - k0 + D - 1;   // tw[r - (k - k0)] = ge(i0 + r - k)
-  int w0 = tw[0], w1 = tw[1], w2 = tw[2], w3 = tw[3];
   int b0 = NEG, b1 = NEG, b2 = NEG, b3 = NEG;
+  if constexpr (KPT % 4 == 0 && KPT <= 16) {
+    // the KPT + 3 table words ge(i0 + r - k) the thread needs start at a
+    // 16-byte boundary: wv[m] = ge at index start + m, m = KPT - 1 + r - t
+    const int start = i0 - k0 + D - 1 - (KPT - 1);
+    int xv[KPT], wv[KPT + 4];
 #pragma unroll
-  for (int t = 0; t < KPT; ++t) {
-    const int x = X[k0 + t];
-    b0 = max(b0, x + w0);
-    b1 = max(b1, x + w1);
-    b2 = max(b2, x + w2);
-    b3 = max(b3, x + w3);
-    if (t + 1 < KPT) {
-      w3 = w2;
-      w2 = w1;
-      w1 = w0;
-      w0 = tw[-(t + 1)];
+    for (int t = 0; t < KPT; t += 4) {
+      const int4 v = *reinterpret_cast<const int4*>(X + k0 + t);
+      xv[t] = v.x;
+      xv[t + 1] = v.y;
+      xv[t + 2] = v.z;
+      xv[t + 3] = v.w;
+    }
+#pragma unroll
+    for (int m = 0; m < KPT + 4; m += 4) {
+      const int4 v = *reinterpret_cast<const int4*>(s.tge + start + m);
+      wv[m] = v.x;
+      wv[m + 1] = v.y;
+      wv[m + 2] = v.z;
+      wv[m + 3] = v.w;
+    }
+#pragma unroll
+    for (int t = 0; t < KPT; ++t) {
+      const int x = xv[t];
+      b0 = max(b0, x + wv[KPT - 1 - t]);
+      b1 = max(b1, x + wv[KPT - t]);
+      b2 = max(b2, x + wv[KPT + 1 - t]);
+      b3 = max(b3, x + wv[KPT + 2 - t]);
+    }
+  } else {
+    const int* tw = s.tge + i0 - k0 + D - 1;   // tw[r - (k - k0)] = ge(i0 + r - k)
+    int w0 = tw[0], w1 = tw[1], w2 = tw[2], w3 = tw[3];
+#pragma unroll
+    for (int t = 0; t < KPT; ++t) {
+      const int x = X[k0 + t];
+      b0 = max(b0, x + w0);
+      b1 = max(b1, x + w1);
+      b2 = max(b2, x + w2);
+      b3 = max(b3, x + w3);
+      if (t + 1 < KPT) {
+        w3 = w2;
+        w2 = w1;
+        w1 = w0;
+        w0 = tw[-(t + 1)];
+      }
     }
   }
   if constexpr (NPART > 1) {
