@@ -576,7 +576,7 @@ __device__ __forceinline__ void gemm_kt(PairSmem<D>& s, const int* P, float* Wb,
   constexpr int LDF = Cfg<D>::LDF, LDB = Cfg<D>::LDB;
   const int lane = threadIdx.x & 63, lr = lane & 31, lk = lane >> 5;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave index, held in a scalar register
-  if constexpr (BF16 && Cfg<D>::NT == 4) {
+  if constexpr (Cfg<D>::NT == 4) {
     if (tri) {
       // The 10 upper tiles: waves 0-3 take two tiles of one row block, which
       // share the kt1 operand, (0,0)+(0,1), (0,2)+(0,3), (1,1)+(1,2),
@@ -587,31 +587,72 @@ __device__ __forceinline__ void gemm_kt(PairSmem<D>& s, const int* P, float* Wb,
       if (w < 4) {
         ti = w < 2 ? 0 : w - 1;
         tj = w == 0 ? 0 : (w == 2 ? 1 : 2);
-        const __bf16* ka = s.u.b.K1 + (ti * 32 + lr) * LDB + 8 * lk;
-        const __bf16* t0 = s.u.b.Tt + (tj * 32 + lr) * LDB + 8 * lk;
-        const __bf16* t1 = t0 + 32 * LDB;
-#pragma unroll 2
-        for (int k0 = 0; k0 < D; k0 += 16) {
-          const bf16x8 a = *reinterpret_cast<const bf16x8*>(ka + k0);
-          const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(t0 + k0);
-          const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(t1 + k0);
-          acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
-          acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
-        }
-        mfma_drain();
       } else if (w < 6) {
         ti = w == 4 ? 1 : 3;
         tj = 3;
-        const __bf16* ka = s.u.b.K1 + (ti * 32 + lr) * LDB + 8 * lk;
-        const __bf16* ta = s.u.b.Tt + (tj * 32 + lr) * LDB + 8 * lk;
+      }
+      const int ia = ti * 32 + lr, ja = tj * 32 + lr;
+      if (w < 4) {
+        if constexpr (BF16) {
+          const __bf16* ka = s.u.b.K1 + ia * LDB + 8 * lk;
+          const __bf16* t0 = s.u.b.Tt + ja * LDB + 8 * lk;
+          const __bf16* t1 = t0 + 32 * LDB;
 #pragma unroll 2
-        for (int k0 = 0; k0 < D / 2; k0 += 16) {
-          const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(ka + k0);
-          const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(ta + k0);
-          const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(ka + k0 + D / 2);
-          const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(ta + k0 + D / 2);
-          acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc0, 0, 0, 0);
-          acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc1, 0, 0, 0);
+          for (int k0 = 0; k0 < D; k0 += 16) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(ka + k0);
+            const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(t0 + k0);
+            const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(t1 + k0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
+          }
+        } else {
+          // one kernel entry for both tiles; operands of step k0 + 2 are read
+          // while the matrix cores run step k0
+          const int Ra = s.R[ia];
+          const float* T = s.u.f.T;
+          float a = kentry<D, WEIGHTED>(s, ia, lk, P, Ra), b0 = T[lk * LDF + ja], b1 = T[lk * LDF + ja + 32];
+          for (int k0 = 0; k0 < D; k0 += 2) {
+            const int kn = (k0 + 2 < D ? k0 + 2 : 0) + lk;
+            const float na = kentry<D, WEIGHTED>(s, ia, kn, P, Ra), nb0 = T[kn * LDF + ja],
+                        nb1 = T[kn * LDF + ja + 32];
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b1, acc1, 0, 0, 0);
+            a = na;
+            b0 = nb0;
+            b1 = nb1;
+          }
+        }
+        mfma_drain();
+      } else if (w < 6) {
+        if constexpr (BF16) {
+          const __bf16* ka = s.u.b.K1 + ia * LDB + 8 * lk;
+          const __bf16* ta = s.u.b.Tt + ja * LDB + 8 * lk;
+#pragma unroll 2
+          for (int k0 = 0; k0 < D / 2; k0 += 16) {
+            const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(ka + k0);
+            const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(ta + k0);
+            const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(ka + k0 + D / 2);
+            const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(ta + k0 + D / 2);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc1, 0, 0, 0);
+          }
+        } else {
+          const int Ra = s.R[ia];
+          const float* T = s.u.f.T;
+          constexpr int H2 = D / 2;
+          float a0 = kentry<D, WEIGHTED>(s, ia, lk, P, Ra), b0 = T[lk * LDF + ja];
+          float a1 = kentry<D, WEIGHTED>(s, ia, lk + H2, P, Ra), b1 = T[(lk + H2) * LDF + ja];
+          for (int k0 = 0; k0 < H2; k0 += 2) {
+            const int kn = (k0 + 2 < H2 ? k0 + 2 : 0) + lk;
+            const float na0 = kentry<D, WEIGHTED>(s, ia, kn, P, Ra), nb0 = T[kn * LDF + ja];
+            const float na1 = kentry<D, WEIGHTED>(s, ia, kn + H2, P, Ra), nb1 = T[(kn + H2) * LDF + ja];
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc1, 0, 0, 0);
+            a0 = na0;
+            b0 = nb0;
+            a1 = na1;
+            b1 = nb1;
+          }
         }
         mfma_drain();
 #pragma unroll
