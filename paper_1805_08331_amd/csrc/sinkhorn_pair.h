@@ -483,6 +483,36 @@ __device__ __forceinline__ void gemm_xk(PairSmem<D>& s, const int* Q, bool trim)
   constexpr int LDF = Cfg<D>::LDF, LDB = Cfg<D>::LDB;
   const int lane = threadIdx.x & 63, lr = lane & 31, lk = lane >> 5;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave index, held in a scalar register
+  if constexpr (!BF16 && Cfg<D>::NT == 4) {
+    // As below for FP32: one kernel entry kt2[j][l] feeds both tiles.
+    int tk0, tk1, tj;
+    xk_tile<D>(w, 0, tk0, tj);
+    xk_tile<D>(w, 1, tk1, tj);
+    const int j = tj * 32 + lr, r0 = tk0 * 32 + lr, r1 = tk1 * 32 + lr;
+    const int lb0 = trim ? tk0 * 32 : 0, lb1 = trim ? tk1 * 32 : 0;
+    const int Sj = s.S[j];
+    const float* X = s.u.f.X;
+    floatx16 acc0 = {}, acc1 = {};
+#pragma unroll 4
+    for (int l0 = lb0; l0 < lb1; l0 += 2) {
+      const int l = l0 + lk;
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(X[r0 * LDF + l], kentry<D, WEIGHTED>(s, j, l, Q, Sj), acc0, 0, 0, 0);
+    }
+#pragma unroll 4
+    for (int l0 = lb1; l0 < D; l0 += 2) {
+      const int l = l0 + lk;
+      const float b = kentry<D, WEIGHTED>(s, j, l, Q, Sj);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(X[r0 * LDF + l], b, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(X[r1 * LDF + l], b, acc1, 0, 0, 0);
+    }
+    mfma_drain();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      s.u.f.T[(tk0 * 32 + 8 * (r >> 2) + 4 * lk + (r & 3)) * LDF + j] = acc0[r];
+      s.u.f.T[(tk1 * 32 + 8 * (r >> 2) + 4 * lk + (r & 3)) * LDF + j] = acc1[r];
+    }
+    return;
+  }
   if constexpr (BF16 && Cfg<D>::NT == 4) {
     // The wave's two tiles share the column block tj, hence the kt2 operand:
     // one chain alone while only the upper tile's l range is live, then both
