@@ -107,7 +107,7 @@ constexpr int PNW = PWGS / 64; // its waves
 constexpr int MAXSUSP = 256;   // suspects handled per half step
 constexpr int QSUSP = 1 << 28; // per-entry marker: entry is suspect number q - QSUSP
 constexpr int HEAD = 40;       // kernel headroom octaves for an input residual within 2^20
-constexpr int SUSP_MARGIN = 30; // octaves between the dropped-term bound and a trusted value
+constexpr int SUSP_MARGIN = 24; // octaves between the dropped-term bound and a trusted value
 
 template <int D>
 struct Cfg {
@@ -1238,7 +1238,8 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, bool w
   const float mxf = (float)xs.mx;
   // Trusted level of a normalised value: everything the contractions drop is
   // below 2^(H + mres + 14 - 126) in these units; keep a 2^-SUSP_MARGIN
-  // relative margin (below FP32 rounding of the contraction sums).
+  // relative margin (the FP32 unit roundoff: no more than the rounding of
+  // the contraction sums themselves).
   const int thr = H + max(xs.mres, 20) + 14 - 126 + SUSP_MARGIN;
   // The X buffer can be cleared now (x was consumed by contraction 1) unless
   // an FP32 X overlaps the BF16 K x buffer still being read.
