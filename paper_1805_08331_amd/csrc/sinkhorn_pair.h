@@ -1075,6 +1075,13 @@ __device__ __forceinline__ void exact_all(PairSmem<D>& s, const SupList<SPT>& xs
     xc = xs.cell_;
     xr = xs.res_;
     nx = xs.n;
+    // a global list that fits the staging area is read from LDS instead
+    if (!dense && xs.n <= PWGS) {
+      const int e = threadIdx.x;
+      s.xs_cell[e] = e < xs.n ? xc[e] : -1;
+      s.xs_res[e] = e < xs.n ? xr[e] : 0.0f;
+      __syncthreads();
+    }
   }
   if (dense) nx = d * d;
   if constexpr (SPT == 1) {
@@ -1120,67 +1127,75 @@ __device__ __forceinline__ void exact_all(PairSmem<D>& s, const SupList<SPT>& xs
     }
   }
   // Four suspects per wave, so that each entry of x is read once for four.
-  constexpr int NT4 = 4;
-  for (int id0 = wave * NT4; id0 < ns; id0 += PNW * NT4) {
-    const int nt = min(NT4, ns - id0);
-    int ti[NT4], tj[NT4], em[NT4];
+  auto generic = [&](const int* xc, const float* xr) {
+    constexpr int NT4 = 4;
+    for (int id0 = wave * NT4; id0 < ns; id0 += PNW * NT4) {
+      const int nt = min(NT4, ns - id0);
+      int ti[NT4], tj[NT4], em[NT4];
 #pragma unroll
-    for (int t = 0; t < NT4; ++t) {
-      const int c = t < nt ? suspCell<D, SPT>(s)[id0 + t] : 0;
-      ti[t] = c / D;
-      tj[t] = c % D;
-      em[t] = QNONE;
-    }
-    for (int e = lane; e < nx; e += 64) {
-      int cell;
-      float x;
-      if (dense) {
-        cell = (e / d) * D + (e % d);
-        x = 1.0f;
-      } else {
-        cell = xc[e];
-        x = cell >= 0 ? xr[e] : 0.0f;
+      for (int t = 0; t < NT4; ++t) {
+        const int c = t < nt ? suspCell<D, SPT>(s)[id0 + t] : 0;
+        ti[t] = c / D;
+        tj[t] = c % D;
+        em[t] = QNONE;
       }
-      if (cell >= 0 && x > 0.0f) {
-        const int kr = cell / D, l = cell % D;
-        const int eb = Px[kr] + Qx[l] + ilog2f(x);
+      for (int e = lane; e < nx; e += 64) {
+        int cell;
+        float x;
+        if (dense) {
+          cell = (e / d) * D + (e % d);
+          x = 1.0f;
+        } else {
+          cell = xc[e];
+          x = cell >= 0 ? xr[e] : 0.0f;
+        }
+        if (cell >= 0 && x > 0.0f) {
+          const int kr = cell / D, l = cell % D;
+          const int eb = Px[kr] + Qx[l] + ilog2f(x);
 #pragma unroll
-        for (int t = 0; t < NT4; ++t)
-          em[t] = max(em[t], eb + s.tge[ti[t] - kr + D - 1] + s.tge[tj[t] - l + D - 1]);
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < NT4; ++t) em[t] = wave_max(em[t]);
-    float acc[NT4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int e = lane; e < nx; e += 64) {
-      int cell;
-      float x;
-      if (dense) {
-        cell = (e / d) * D + (e % d);
-        x = 1.0f;
-      } else {
-        cell = xc[e];
-        x = cell >= 0 ? xr[e] : 0.0f;
-      }
-      if (cell >= 0 && x > 0.0f) {
-        const int kr = cell / D, l = cell % D;
-        const int eb = Px[kr] + Qx[l];
-#pragma unroll
-        for (int t = 0; t < NT4; ++t) {
-          const int i1 = ti[t] - kr + D - 1, i2 = tj[t] - l + D - 1;
-          float mm = x * s.tgm[i1] * s.tgm[i2];
-          if (WEIGHTED) mm *= (s.tc1[i1] + s.tc1[i2]);
-          acc[t] += ldx(mm, eb + s.tge[i1] + s.tge[i2] - em[t]);
+          for (int t = 0; t < NT4; ++t)
+            em[t] = max(em[t], eb + s.tge[ti[t] - kr + D - 1] + s.tge[tj[t] - l + D - 1]);
         }
       }
-    }
 #pragma unroll
-    for (int t = 0; t < NT4; ++t) acc[t] = wave_sum(acc[t]);
-    if (lane == 0) {
+      for (int t = 0; t < NT4; ++t) em[t] = wave_max(em[t]);
+      float acc[NT4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      for (int e = lane; e < nx; e += 64) {
+        int cell;
+        float x;
+        if (dense) {
+          cell = (e / d) * D + (e % d);
+          x = 1.0f;
+        } else {
+          cell = xc[e];
+          x = cell >= 0 ? xr[e] : 0.0f;
+        }
+        if (cell >= 0 && x > 0.0f) {
+          const int kr = cell / D, l = cell % D;
+          const int eb = Px[kr] + Qx[l];
 #pragma unroll
-      for (int t = 0; t < NT4; ++t)
-        if (t < nt) finish(id0 + t, ti[t] * D + tj[t], em[t], acc[t]);
+          for (int t = 0; t < NT4; ++t) {
+            const int i1 = ti[t] - kr + D - 1, i2 = tj[t] - l + D - 1;
+            float mm = x * s.tgm[i1] * s.tgm[i2];
+            if (WEIGHTED) mm *= (s.tc1[i1] + s.tc1[i2]);
+            acc[t] += ldx(mm, eb + s.tge[i1] + s.tge[i2] - em[t]);
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < NT4; ++t) acc[t] = wave_sum(acc[t]);
+      if (lane == 0) {
+#pragma unroll
+        for (int t = 0; t < NT4; ++t)
+          if (t < nt) finish(id0 + t, ti[t] * D + tj[t], em[t], acc[t]);
+      }
     }
+  };
+  if constexpr (SPT == 0) {
+    if (!dense && xs.n <= PWGS) generic(s.xs_cell, s.xs_res);
+    else generic(xc, xr);
+  } else {
+    generic(xc, xr);
   }
   __syncthreads();
 }
