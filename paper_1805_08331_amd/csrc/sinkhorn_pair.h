@@ -1429,10 +1429,16 @@ __device__ __forceinline__ void y_update(PairSmem<D>& s, const float* Wb, bool w
   }
   __syncthreads();
 
-  // New scales: natural (-R, -S) plus the centres (rho, sigma) of sweep 1.
-  for (int r = tid; r < D; r += PWGS) {
-    Py[r] = s.fit[1][0][r] != INT_MIN ? midrange(s.fit[1][0], s.fit[1][1], r) - s.R[r] : NEG;
-    Qy[r] = s.fit[1][2][r] != INT_MIN ? midrange(s.fit[1][2], s.fit[1][3], r) - s.S[r] : NEG;
+  // New scales: natural (-R, -S) plus the centres (rho, sigma) of sweep 1,
+  // by the last threads, which hold no support entry unless the support
+  // fills the lists (entries sit on threads 0, 1, ...).
+  static_assert(D <= PWGS, "one scale per thread");
+  {
+    const int r = PWGS - 1 - tid;
+    if (r < D) {
+      Py[r] = s.fit[1][0][r] != INT_MIN ? midrange(s.fit[1][0], s.fit[1][1], r) - s.R[r] : NEG;
+      Qy[r] = s.fit[1][2][r] != INT_MIN ? midrange(s.fit[1][2], s.fit[1][3], r) - s.S[r] : NEG;
+    }
   }
   ESum acc{NEG, 0.0};
   int maxres = 0;
