@@ -372,14 +372,14 @@ __device__ __forceinline__ float kentry(const PairSmem<D>& s, int i, int k, cons
   return v;
 }
 
-// BF16 kernels of one application into LDS: K1[i][k] from P and R, K2[j][l]
-// from Q and S, 16 consecutive entries of one row per thread and step.  An
-// entry bf16(gm) 2^(P_k + ge - R_i) is assembled directly as a BF16 bit
-// pattern by adding the exponent shift to the table word; results below the
-// smallest normal BF16 (2^-126, at least 2^-166 below the row maximum) become
-// 0 or a subnormal pattern.
+// BF16 kernels of one application into LDS: K1[i][k] from P (as s.P7) and R,
+// K2[j][l] from Q (as s.Q7) and S, 16 consecutive entries of one row of both
+// per thread and step.  An entry bf16(gm) 2^(P_k + ge - R_i) is assembled
+// directly as a BF16 bit pattern by adding the exponent shift to the table
+// word; results below the smallest normal BF16 (2^-126, at least 2^-166
+// below the row maximum) become 0 or a subnormal pattern.
 template <int D>
-__device__ __forceinline__ void build_kernels_bf16(PairSmem<D>& s, const int* P, const int* Q, int d) {
+__device__ __forceinline__ void build_kernels_bf16(PairSmem<D>& s, int d) {
   constexpr int LDB = Cfg<D>::LDB;
   // Rows i >= d feed only output rows/columns that are never read, so they
   // are skipped; chunks of columns k >= d hold exact zeros (P_k = NEG) and
@@ -858,6 +858,9 @@ __device__ __forceinline__ void contract(PairSmem<D>& s, const int* P, const int
   }
 }
 
+template <int D>
+__device__ __forceinline__ void prep_update(PairSmem<D>& s);
+
 // (K x) on the grid for input scales P, Q (residual already in the X buffer of
 // the matching format) into the K x buffer, scaled by 2^-(R_i + S_j).  `trim`:
 // x vanishes below the diagonal; `tri`: only cells on or above it are read.
@@ -875,7 +878,7 @@ __device__ __forceinline__ float* apply_K(PairSmem<D>& s, const int* P, const in
   __syncthreads();
   float* Wb = wbuf<D>(s, lowp);
   if (lowp) {
-    build_kernels_bf16<D>(s, P, Q, d);
+    build_kernels_bf16<D>(s, d);
     __syncthreads();
     contract<D, true, false, false>(s, P, Q, Wb, trim, tri);
   } else {
