@@ -144,8 +144,9 @@ int sinkhorn_dist_batch(pdsink_ctx* ctx, int64_t n_pairs,
  *         the ground space, every grid cell and the diagonal bin) computed
  *         by separable min-plus passes over the grid
  * so that lower <= L_C(a, b) <= upper up to rounding.  Both are NaN for a pair
- * whose status has PDSINK_ST_NONFINITE or PDSINK_ST_LOG_PATH, and 0 for an
- * empty pair.  The K
+ * whose status has PDSINK_ST_NONFINITE, and 0 for an empty pair; a pair solved
+ * by the log-domain path (PDSINK_ST_LOG_PATH) gets them from its log
+ * scalings, by the same definitions.  The K
  * applications inside are exact sums over the two supports, O(|supp a| |supp b|)
  * per pair; the transforms cost O(d^3) per pair.  Other arguments, errors and
  * the workspace are those of sinkhorn_dist_batch. */

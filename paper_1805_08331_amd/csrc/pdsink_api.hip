@@ -314,6 +314,8 @@ int run_pairs(const pdsink_ctx* ctx, int64_t n_pairs, const float* ha, const flo
   lp.status = status;
   lp.upper = ex.upper;
   lp.lower = ex.lower;
+  lp.scratch = ex.lists;   // the slots' list areas, free once the solve launches are done
+  lp.scratch_stride = slot_bytes(ctx->D);
   return launch_log_path(lp, ex.n_slots, st) ? PDSINK_EDEVICE : PDSINK_OK;
 }
 

@@ -164,6 +164,154 @@ __device__ double lse_delta(LogSmem& S, int src, int d, double xD, double ig) {
   return m + log(s);
 }
 
+// The error-control bounds of section 3 for the final log scalings (the
+// same definitions as the scaled path's: lower = <alpha^{c cbar}, a> +
+// <alpha^c, b> with alpha = gamma log u over the whole ground space; upper =
+// <R, C> of the rounded plan, Proposition 4).
+
+// In place over the rows (ROWS) or columns of the d x d grid g (row stride
+// d + 1): g[r][o] <- min over x of c(o - x) + g[r][x]; one wave per line.
+template <bool ROWS>
+__device__ void log_minplus(double* g, const double* c1d, int d) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int LG = d + 1;
+  for (int line = wave; line < d; line += LNW) {
+    double acc[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+    for (int x = 0; x < d; ++x) {
+      const double gv = ROWS ? g[line * LG + x] : g[x * LG + line];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int o = min(lane + 64 * q, d - 1);
+        acc[q] = fmin(acc[q], c1d[o - x + d - 1] + gv);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int o = lane + 64 * q;
+      if (o < d) {
+        if (ROWS) g[line * LG + o] = acc[q];
+        else g[o * LG + line] = acc[q];
+      }
+    }
+  }
+}
+
+__device__ double log_lower_bound(LogSmem& S, double* g, int d, double gamma, double luD, double aD, double bD) {
+  const int tid = threadIdx.x, LG = d + 1;
+  for (int c = tid; c < d * LG; c += LWG) g[c] = INFINITY;
+  __syncthreads();
+  const double alD = gamma * luD;
+  double mD = -alD;
+  for (int e = tid; e < S.n[0]; e += LWG) {
+    const int c = S.src[0][e].cell, i = c >> 16, j = c & 0xFFFF;
+    const double al = gamma * S.src[0][e].ls;
+    g[i * LG + j] = -al;
+    mD = fmin(mD, S.cdd[j - i + d - 1] - al);
+  }
+  const double acD = block_min<LNW>(mD, S.red);   // alpha^c at the diagonal bin
+  log_minplus<true>(g, S.c1d, d);
+  __syncthreads();
+  log_minplus<false>(g, S.c1d, d);
+  __syncthreads();
+  double mg = -acD;
+  for (int c = tid; c < d * d; c += LWG) {
+    const int i = c / d, j = c % d;
+    const double cd = S.cdd[j - i + d - 1];
+    const double v = fmin(g[i * LG + j], cd - alD);   // alpha^c on the grid
+    g[i * LG + j] = -v;
+    mg = fmin(mg, cd - v);
+  }
+  const double accD = block_min<LNW>(mg, S.red);  // alpha^{c cbar} at the diagonal bin
+  double sb = 0.0;
+  for (int e = tid; e < S.n[1]; e += LWG) {
+    const int c = S.src[1][e].cell, i = c >> 16, j = c & 0xFFFF;
+    sb -= exp(S.lt[1][e]) * g[i * LG + j];
+  }
+  sb = block_sum<LNW>(sb, S.red) + bD * acD;
+  log_minplus<true>(g, S.c1d, d);
+  __syncthreads();
+  log_minplus<false>(g, S.c1d, d);
+  __syncthreads();
+  double sa = 0.0;
+  for (int e = tid; e < S.n[0]; e += LWG) {
+    const int c = S.src[0][e].cell, i = c >> 16, j = c & 0xFFFF;
+    sa += exp(S.lt[0][e]) * fmin(g[i * LG + j], S.cdd[j - i + d - 1] - acD);
+  }
+  sa = block_sum<LNW>(sa, S.red) + aD * accD;
+  return sa + sb;
+}
+
+// Upper bound: on entry lk[0] holds log (K v) at the cells of supp(a) and
+// lkD0 at the diagonal bin, for the final (u, v).  The log scalings of both
+// sides are left scaled by X and Y.
+__device__ double log_upper_bound(LogSmem& S, int d, double ig, double luD, double lvD, double lkD0, double aD,
+                                  double bD, bool p2) {
+  const int tid = threadIdx.x;
+  // X = min(a / r(P), 1) on u
+  for (int e = tid; e < S.n[0]; e += LWG)
+    S.src[0][e].ls += fmin(S.lt[0][e] - S.src[0][e].ls - S.lk[0][e], 0.0);
+  luD += fmin(log(aD) - luD - lkD0, 0.0);
+  __syncthreads();
+  // Y = min(b / c(P'), 1) on v; e_c = b - c(P'') into lk[1]
+  for (int e = tid; e < S.n[1]; e += LWG) {
+    const int c = S.src[1][e].cell, i = c >> 16, j = c & 0xFFFF;
+    const double xD = luD - S.cdd[j - i + d - 1] * ig;
+    S.lk[1][e] = p2 ? lse_at<true>(S, 0, i, j, d, xD, ig) : lse_at<false>(S, 0, i, j, d, xD, ig);
+  }
+  const double l1D = lse_delta(S, 0, d, luD, ig);
+  double ec1 = 0.0, eccd = 0.0;
+  for (int e = tid; e < S.n[1]; e += LWG) {
+    const int c = S.src[1][e].cell, i = c >> 16, j = c & 0xFFFF;
+    S.src[1][e].ls += fmin(S.lt[1][e] - S.src[1][e].ls - S.lk[1][e], 0.0);
+    const double ec = exp(S.lt[1][e]) - exp(S.src[1][e].ls + S.lk[1][e]);
+    S.lk[1][e] = ec;
+    ec1 += fabs(ec);
+    eccd += ec * S.cdd[j - i + d - 1];
+  }
+  lvD += fmin(log(bD) - lvD - l1D, 0.0);
+  const double ecD = bD - exp(lvD + l1D);
+  __syncthreads();
+  // e_r = a - r(P'') into lk[0]
+  for (int e = tid; e < S.n[0]; e += LWG) {
+    const int c = S.src[0][e].cell, i = c >> 16, j = c & 0xFFFF;
+    const double xD = lvD - S.cdd[j - i + d - 1] * ig;
+    S.lk[0][e] = p2 ? lse_at<true>(S, 1, i, j, d, xD, ig) : lse_at<false>(S, 1, i, j, d, xD, ig);
+  }
+  const double l0D = lse_delta(S, 1, d, lvD, ig);
+  double ercd = 0.0;
+  for (int e = tid; e < S.n[0]; e += LWG) {
+    const int c = S.src[0][e].cell, i = c >> 16, j = c & 0xFFFF;
+    const double er = exp(S.lt[0][e]) - exp(S.src[0][e].ls + S.lk[0][e]);
+    S.lk[0][e] = er;
+    ercd += er * S.cdd[j - i + d - 1];
+  }
+  const double erD = aD - exp(luD + l0D);
+  __syncthreads();
+  // <P'', C> and the rank-one term, both over the two supports and Delta
+  double g = 0.0, tr = 0.0;
+  for (int e = tid; e < S.n[0]; e += LWG) {
+    const int c = S.src[0][e].cell, i = c >> 16, j = c & 0xFFFF;
+    const double lu = S.src[0][e].ls, er = S.lk[0][e];
+    for (int f = 0; f < S.n[1]; ++f) {
+      const int c2 = S.src[1][f].cell, k = c2 >> 16, l = c2 & 0xFFFF;
+      const double C = S.c1d[i - k + d - 1] + S.c1d[j - l + d - 1];
+      g += exp(lu + S.src[1][f].ls - C * ig) * C;
+      tr += er * S.lk[1][f] * C;
+    }
+    const double cd = S.cdd[j - i + d - 1];
+    g += exp(lu + lvD - cd * ig) * cd;
+  }
+  for (int f = tid; f < S.n[1]; f += LWG) {
+    const int c = S.src[1][f].cell, i = c >> 16, j = c & 0xFFFF;
+    const double cd = S.cdd[j - i + d - 1];
+    g += exp(luD + S.src[1][f].ls - cd * ig) * cd;
+  }
+  const double gs = block_sum<LNW>(g, S.red);
+  const double en = block_sum<LNW>(ec1, S.red) + fabs(ecD);
+  const double tt = block_sum<LNW>(tr, S.red) + ecD * block_sum<LNW>(ercd, S.red) + erD * block_sum<LNW>(eccd, S.red);
+  return gs + (en > 0.0 ? tt / en : 0.0);
+}
+
 __device__ void solve_log_pair(const LogParams& prm, LogSmem& S, long long pair) {
   const int d = prm.d, tid = threadIdx.x;
   const double ig = 1.0 / prm.gamma;
@@ -258,6 +406,12 @@ __device__ void solve_log_pair(const LogParams& prm, LogSmem& S, long long pair)
     g += exp(luD + S.src[1][f].ls - cd * ig) * cd;
   }
   const double cost = block_sum<LNW>(g, S.red);
+  double lo = NAN, up = NAN;
+  if (prm.lower && t > 0) {
+    double* grid = reinterpret_cast<double*>(prm.scratch + (size_t)blockIdx.x * prm.scratch_stride);
+    lo = log_lower_bound(S, grid, d, prm.gamma, luD, aD, bD);
+  }
+  if (prm.upper && t > 0) up = log_upper_bound(S, d, ig, luD, lvD, lkD0, aD, bD, p2);
   if (tid == 0) {
     int st = ST_LOG;
     if (!(err <= prm.tol)) st |= 1;
@@ -267,8 +421,8 @@ __device__ void solve_log_pair(const LogParams& prm, LogSmem& S, long long pair)
     prm.iters[2 * pair + 1] = t;
     prm.err[pair] = (float)err;
     prm.status[pair] = st;
-    if (prm.upper) prm.upper[pair] = NAN;
-    if (prm.lower) prm.lower[pair] = NAN;
+    if (prm.upper) prm.upper[pair] = up;
+    if (prm.lower) prm.lower[pair] = lo;
   }
 }
 

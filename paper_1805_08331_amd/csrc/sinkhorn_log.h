@@ -21,8 +21,10 @@ struct LogParams {
   int* iters;
   float* err;
   int* status;
-  double* upper;   // optional: set to NaN for the pairs this path solves
+  double* upper;   // optional error-control bounds of the pairs this path solves
   double* lower;
+  char* scratch;          // per workgroup: scratch_stride bytes, at least 8 d (d + 1)
+  size_t scratch_stride;
 };
 
 constexpr int LOG_CAP = 1024;   // support cells per side the log-domain path takes

@@ -319,8 +319,10 @@ def test_tiny_gamma_same_schedule(pds, d, g, max_iter, log_path):
         assert rel(cost[q], ref) <= FP32_RTOL, (q, st[q], cost[q], ref)
 
 
-def test_log_path_bounds_are_nan(pds):
-    """Bounds are not computed for a pair solved by the log-domain path."""
+def test_log_path_bounds_match_oracle(pds):
+    """Bounds of pairs solved by the log-domain path against the oracle's
+    dense rounding and c-transforms at the same log scalings (upper 1e-5
+    relative, lower within 1e-5 of the upper bound)."""
     d, g = 32, 2e-5
     D1s, D2s = pdgen.pairs_batch(31, 2, 10, 60)
     with pds.Context(d, g, tol=1e-4, max_iter=300) as ctx:
@@ -332,8 +334,20 @@ def test_log_path_bounds_are_nan(pds):
         torch.cuda.synchronize()
     st = r.status.cpu().numpy()
     assert np.all(st & pds._lib.PDSINK_ST_LOG_PATH), st
-    assert np.all(np.isnan(r.upper.cpu().numpy())) and np.all(np.isnan(r.lower.cpu().numpy()))
-    assert np.all(np.isfinite(r.cost.cpu().numpy()))
+    h = hist.cpu().numpy()
+    C = dense_C(d)
+    up, lo = r.upper.cpu().numpy(), r.lower.cpu().numpy()
+    for q in range(2):
+        a_, b_ = ground.marginals(h[q], h[2 + q])
+        sa = a_ > 0
+        _, t, _, lu, lv = sinkhorn.solve_log(a_[sa], b_, C[sa, :], g, tol=0.0, max_iter=int(r.iters[q].sum()))
+        log_u = np.full(a_.shape, -np.inf)
+        log_u[sa] = lu
+        ou = bounds.upper_bound(log_u, lv, a_, b_, C, g)
+        ol = bounds.lower_bound(log_u, a_, b_, C, g)
+        assert rel(up[q], ou) <= FP32_RTOL, (q, up[q], ou)
+        assert abs(lo[q] - ol) <= FP32_RTOL * abs(ou), (q, lo[q], ol)
+        assert lo[q] <= up[q]   # (the Sinkhorn cost of an unconverged plan need not lie between them)
 
 
 def test_alone_equals_in_batch(pds):
