@@ -107,7 +107,7 @@ def run_gpu(precision: str, steps: int, warmup: int, pts_d, off_d, switch_tol: f
 
 
 def cpu_baseline(budget_s: float = 20.0):
-    """FP64 oracle on config-2 pairs 0, 1, ... until ~budget_s of CPU work."""
+    """FP64 oracle on pairs 0, 1, ... of the benchmark batch until ~budget_s of CPU work."""
     import pdgen
     from oracle import ground, sinkhorn
     try:
@@ -128,7 +128,7 @@ def cpu_baseline(budget_s: float = 20.0):
         if t_used >= budget_s:
             break
     return {"value": its / t_used, "unit": "pair-it/s", "cores": int(blas_threads), "kind": "oracle",
-            "sample": f"config-2 pairs 0..{done - 1} ({its} pair-iterations, {t_used:.1f} s), FP64 dense "
+            "sample": f"benchmark batch (1024 pairs, d=100) pairs 0..{done - 1} ({its} pair-iterations, {t_used:.1f} s), FP64 dense "
                       f"(d^2+1)-point kernel on the host, cost matrix built once outside the timing; "
                       f"os.cpu_count()={os.cpu_count()}"}
 

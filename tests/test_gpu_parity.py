@@ -78,7 +78,7 @@ def test_discretize_bit_exact(pds):
         assert bad.item() == 4 and mass.item() == 1 and hist.sum().item() == 1
 
 
-def test_config1_single_pair(pds):
+def test_single_pair_d32_300_iterations(pds):
     """d=32, gamma=1e-2, 300 iterations, 20 and 30 points (seed 0)."""
     D1, D2 = pdgen.pair_single(0)
     d, g = 32, 1e-2
@@ -108,7 +108,7 @@ def test_batch_same_schedule(pds, d, g, lo, hi):
         assert abs(ro.iters - t) <= 1
 
 
-def test_config2_sampled_full_batch(pds):
+def test_benchmark_batch_sampled(pds):
     """1024 pairs at d=100, gamma=1e-3, tol=1e-3 (the benchmark's launch); three
     pairs re-run by the oracle at the GPU's iteration counts."""
     d, g = 100, 1e-3

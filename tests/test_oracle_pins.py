@@ -277,7 +277,7 @@ def test_log_domain_on_support_rows_matches_full():
         assert math.isclose(r.err, el, rel_tol=1e-6, abs_tol=1e-13)
 
 
-def test_config1_reference_run():
+def test_single_pair_reference_run():
     """Single pair, d=32, gamma=1e-2, 300 iterations: oracle and log-domain agree."""
     D1, D2 = pdgen.pair_single(0)
     d = 32
