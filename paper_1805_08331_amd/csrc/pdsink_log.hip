@@ -144,6 +144,79 @@ __device__ __forceinline__ double lse_at(const LogSmem& S, int src, int i, int j
   return m + log((s0 + s1) + (s2 + s3));
 }
 
+// The same log-sum-exp with SPLIT lanes per target cell (adjacent lanes of
+// a quad), each over every SPLIT-th source; the partial maxima and sums are
+// combined across the quad.  Every lane of the group returns the result.
+template <bool P2, int SPLIT>
+__device__ __forceinline__ double lse_split(const LogSmem& S, int src, int i, int j, int d, double xD, double ig,
+                                            int part) {
+  const int ns = S.n[src];
+  const Src* sr = S.src[src];
+  const double* ci = S.c1d + i + d - 1;
+  const double* cj = S.c1d + j + d - 1;
+  const double igd = ig / ((double)d * (double)d);
+  auto x_of = [&](int e) {
+    const Src q = sr[e];
+    const int k = q.cell >> 16, l = q.cell & 0xFFFF;
+    if constexpr (P2) {
+      const int di = i - k, dj = j - l;
+      return q.ls - (double)(di * di + dj * dj) * igd;
+    } else {
+      return q.ls - (ci[-k] + cj[-l]) * ig;
+    }
+  };
+  double m0 = part == 0 ? xD : -INFINITY, m1 = -INFINITY;
+  int e = part;
+  for (; e + SPLIT < ns; e += 2 * SPLIT) {
+    m0 = fmax(m0, x_of(e));
+    m1 = fmax(m1, x_of(e + SPLIT));
+  }
+  if (e < ns) m0 = fmax(m0, x_of(e));
+  double m = fmax(m0, m1);
+  m = fmax(m, dpp_d<DPP_QXOR1>(m));
+  if constexpr (SPLIT == 4) m = fmax(m, dpp_d<DPP_QXOR2>(m));
+  if (m == -INFINITY) return -INFINITY;
+  double s0 = part == 0 ? exp_neg(xD - m) : 0.0, s1 = 0.0;
+  e = part;
+  for (; e + SPLIT < ns; e += 2 * SPLIT) {
+    s0 += exp_neg(x_of(e) - m);
+    s1 += exp_neg(x_of(e + SPLIT) - m);
+  }
+  if (e < ns) s0 += exp_neg(x_of(e) - m);
+  double sum = s0 + s1;
+  sum += dpp_d<DPP_QXOR1>(sum);
+  if constexpr (SPLIT == 4) sum += dpp_d<DPP_QXOR2>(sum);
+  return m + log(sum);
+}
+
+// lk[tgt][e] = LSE over side `src` (plus the diagonal bin, log scaling xDb)
+// of ls - C / gamma at every cell e of side tgt: four lanes per cell when
+// the targets fit a quarter of the workgroup, two when they fit half.
+template <bool P2>
+__device__ void apply_lse(LogSmem& S, int tgt, int src, int d, double xDb, double ig) {
+  const int nt = S.n[tgt], tid = threadIdx.x;
+  if (nt <= LWG / 4) {
+    const int t = tid >> 2, part = tid & 3;
+    if (t < nt) {
+      const int c = S.src[tgt][t].cell, i = c >> 16, j = c & 0xFFFF;
+      const double v = lse_split<P2, 4>(S, src, i, j, d, xDb - S.cdd[j - i + d - 1] * ig, ig, part);
+      if (part == 0) S.lk[tgt][t] = v;
+    }
+  } else if (nt <= LWG / 2) {
+    const int t = tid >> 1, part = tid & 1;
+    if (t < nt) {
+      const int c = S.src[tgt][t].cell, i = c >> 16, j = c & 0xFFFF;
+      const double v = lse_split<P2, 2>(S, src, i, j, d, xDb - S.cdd[j - i + d - 1] * ig, ig, part);
+      if (part == 0) S.lk[tgt][t] = v;
+    }
+  } else {
+    for (int e = tid; e < nt; e += LWG) {
+      const int c = S.src[tgt][e].cell, i = c >> 16, j = c & 0xFFFF;
+      S.lk[tgt][e] = lse_at<P2>(S, src, i, j, d, xDb - S.cdd[j - i + d - 1] * ig, ig);
+    }
+  }
+}
+
 // LSE over the sources of side `src` plus xD of ls - c_Delta / gamma: the
 // K application at the diagonal bin (C_Delta,Delta = 0).
 __device__ double lse_delta(LogSmem& S, int src, int d, double xD, double ig) {
@@ -253,11 +326,9 @@ __device__ double log_upper_bound(LogSmem& S, int d, double ig, double luD, doub
   luD += fmin(log(aD) - luD - lkD0, 0.0);
   __syncthreads();
   // Y = min(b / c(P'), 1) on v; e_c = b - c(P'') into lk[1]
-  for (int e = tid; e < S.n[1]; e += LWG) {
-    const int c = S.src[1][e].cell, i = c >> 16, j = c & 0xFFFF;
-    const double xD = luD - S.cdd[j - i + d - 1] * ig;
-    S.lk[1][e] = p2 ? lse_at<true>(S, 0, i, j, d, xD, ig) : lse_at<false>(S, 0, i, j, d, xD, ig);
-  }
+  if (p2) apply_lse<true>(S, 1, 0, d, luD, ig);
+  else apply_lse<false>(S, 1, 0, d, luD, ig);
+  __syncthreads();
   const double l1D = lse_delta(S, 0, d, luD, ig);
   double ec1 = 0.0, eccd = 0.0;
   for (int e = tid; e < S.n[1]; e += LWG) {
@@ -272,11 +343,9 @@ __device__ double log_upper_bound(LogSmem& S, int d, double ig, double luD, doub
   const double ecD = bD - exp(lvD + l1D);
   __syncthreads();
   // e_r = a - r(P'') into lk[0]
-  for (int e = tid; e < S.n[0]; e += LWG) {
-    const int c = S.src[0][e].cell, i = c >> 16, j = c & 0xFFFF;
-    const double xD = lvD - S.cdd[j - i + d - 1] * ig;
-    S.lk[0][e] = p2 ? lse_at<true>(S, 1, i, j, d, xD, ig) : lse_at<false>(S, 1, i, j, d, xD, ig);
-  }
+  if (p2) apply_lse<true>(S, 0, 1, d, lvD, ig);
+  else apply_lse<false>(S, 0, 1, d, lvD, ig);
+  __syncthreads();
   const double l0D = lse_delta(S, 1, d, lvD, ig);
   double ercd = 0.0;
   for (int e = tid; e < S.n[0]; e += LWG) {
@@ -369,22 +438,18 @@ __device__ void solve_log_pair(const LogParams& prm, LogSmem& S, long long pair)
     luD = ltD0 - lkD0;
     __syncthreads();
     // v-update: v = b / K^T u
-    for (int e = tid; e < S.n[1]; e += LWG) {
-      const int c = S.src[1][e].cell, i = c >> 16, j = c & 0xFFFF;
-      S.lk[1][e] = p2 ? lse_at<true>(S, 0, i, j, d, luD - S.cdd[j - i + d - 1] * ig, ig)
-                      : lse_at<false>(S, 0, i, j, d, luD - S.cdd[j - i + d - 1] * ig, ig);
-    }
+    if (p2) apply_lse<true>(S, 1, 0, d, luD, ig);
+    else apply_lse<false>(S, 1, 0, d, luD, ig);
+    __syncthreads();
     const double lkD1 = lse_delta(S, 0, d, luD, ig);
     for (int e = tid; e < S.n[1]; e += LWG) S.src[1][e].ls = S.lt[1][e] - S.lk[1][e];
     lvD = ltD1 - lkD1;
     __syncthreads();
     ++t;
     // K v for the next check and u-update
-    for (int e = tid; e < S.n[0]; e += LWG) {
-      const int c = S.src[0][e].cell, i = c >> 16, j = c & 0xFFFF;
-      S.lk[0][e] = p2 ? lse_at<true>(S, 1, i, j, d, lvD - S.cdd[j - i + d - 1] * ig, ig)
-                      : lse_at<false>(S, 1, i, j, d, lvD - S.cdd[j - i + d - 1] * ig, ig);
-    }
+    if (p2) apply_lse<true>(S, 0, 1, d, lvD, ig);
+    else apply_lse<false>(S, 0, 1, d, lvD, ig);
+    __syncthreads();
     lkD0 = lse_delta(S, 1, d, lvD, ig);
   }
   // Proposition 3's value <P_t, C> summed over the supports and the Delta blocks.
