@@ -1087,16 +1087,19 @@ __device__ __forceinline__ void exact_all(PairSmem<D>& s, const SupList<SPT>& xs
     }
   }
   if (dense) nx = d * d;
-  if constexpr (SPT == 1) {
-    if (!dense) {
-      // PWGS / 64 staged entries per lane, kept in registers for both passes
+  {
+    // staged x (a register list, or a global list of at most PWGS cells):
+    // PWGS / 64 entries per lane, kept in registers for both passes
+    bool small = true;
+    if constexpr (SPT == 0) small = xs.n <= PWGS;
+    if (!dense && small) {
       constexpr int EPL = PWGS / 64;
       int kr[EPL], l[EPL], eb[EPL];
       float xm[EPL];
 #pragma unroll
       for (int u = 0; u < EPL; ++u) {
-        const int cell = xc[lane + 64 * u];
-        const float x = xr[lane + 64 * u];
+        const int cell = s.xs_cell[lane + 64 * u];
+        const float x = s.xs_res[lane + 64 * u];
         const bool ok = cell >= 0 && x > 0.0f;
         kr[u] = ok ? cell / D : 0;
         l[u] = ok ? cell % D : 0;
@@ -1194,12 +1197,7 @@ __device__ __forceinline__ void exact_all(PairSmem<D>& s, const SupList<SPT>& xs
       }
     }
   };
-  if constexpr (SPT == 0) {
-    if (!dense && xs.n <= PWGS) generic(s.xs_cell, s.xs_res);
-    else generic(xc, xr);
-  } else {
-    generic(xc, xr);
-  }
+  generic(xc, xr);
   __syncthreads();
 }
 
