@@ -182,7 +182,7 @@ def measured_traffic():
     return rec.get("traffic_bytes") if rec.get("source_hash") == source_hash() else None
 
 
-def write_traffic(fetch_csv: str, write_csv: str):
+def write_traffic(fetch_csv: str, write_csv: str, out: str | None = None):
     """Summarise two rocprofv3 counter runs of ``--pmc-probe`` (FETCH_SIZE, then
     WRITE_SIZE, KiB per dispatch) into the traffic record of the pair kernel,
     scaled by what the counters read for the 256 MiB calibration copy."""
@@ -214,7 +214,8 @@ def write_traffic(fetch_csv: str, write_csv: str):
            "traffic_bytes": int(round(traffic)),
            # two d x d FP32 histograms per pair in; cost, 2 iteration counts, error, status, route byte out
            "algorithmic_bytes": NPAIRS * (2 * 100 * 100 * 4 + 8 + 8 + 4 + 4 + 1)}
-    out = os.path.join(ROOT, "profiles", "sinkhorn_pair_kernel_d100_1024pairs_traffic.json")
+    if out is None:
+        out = os.path.join(ROOT, "profiles", "sinkhorn_pair_kernel_d100_1024pairs_traffic.json")
     with open(out, "w") as fh:
         json.dump(rec, fh, indent=1)
         fh.write("\n")
