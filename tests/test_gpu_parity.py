@@ -350,6 +350,18 @@ def test_log_path_bounds_match_oracle(pds):
         assert lo[q] <= up[q]   # (the Sinkhorn cost of an unconverged plan need not lie between them)
 
 
+def test_alone_equals_in_large_batch(pds):
+    """In a batch larger than the device (launched in support order) a pair's
+    result is bitwise the one it gets alone."""
+    d, g = 32, 5e-3
+    D1s, D2s = pdgen.pairs_batch(19, 300, 5, 120)
+    with pds.Context(d, g, tol=1e-4, max_iter=2000, precision="bf16") as ctx:
+        cost, iters, err, st, _ = run_pairs(pds, ctx, D1s, D2s)
+        for q in (0, 151, 299):
+            c1, i1, e1, s1, _ = run_pairs(pds, ctx, [D1s[q]], [D2s[q]])
+            assert c1[0] == cost[q] and np.array_equal(i1[0], iters[q]) and e1[0] == err[q]
+
+
 def test_alone_equals_in_batch(pds):
     """A pair's result does not depend on the batch it runs in (bitwise)."""
     d, g = 64, 2e-3
