@@ -247,6 +247,56 @@ def gamma_sweep(pts_d, off_d, switch_tol: float):
                 "flagged": int(((st & 6) != 0).sum()), "max_iter": int(((st & 1) != 0).sum())}), flush=True)
 
 
+def serve_bench(seconds: float, rate: float = 2000.0, k: int = 10, slots: int = 2, max_pairs: int = 512):
+    """Serving loop on a Poisson stream: ``rate`` requests/s for ``seconds``
+    (after a 1 s warm-up stream), half distances and half assignments to k
+    resident centroids, grids 50, 100 and 200, lognormal(5, 0.7) point counts;
+    gamma = 1e-3, stop at marginal error 1e-3.  Prints one JSON line with the
+    latency percentiles (arrival to result on the host) and the throughput."""
+    import torch
+    import pdgen
+    import paper_1805_08331_amd as pds
+    from paper_1805_08331_amd import serve
+
+    grids = (50, 100, 200)
+    cdiags, _ = pdgen.kmeans_set(1, k, n_templates=k)
+    cents = {}
+    for d in grids:
+        with pds.Context(d, GAMMA) as ctx:
+            pts, off = pdgen.to_csr(cdiags)
+            h, _, _ = pds.pd_discretize(ctx, torch.from_numpy(pts).cuda(), torch.from_numpy(off).cuda())
+            torch.cuda.synchronize()
+            cents[d] = h.contiguous()
+    srv = serve.Server(grids, GAMMA, centroids=cents, slots=slots, max_pairs=max_pairs, tol=TOL, max_iter=5000,
+                       precision="bf16", switch_tol=0.8e-3)
+    serve.run_stream(srv, pdgen.serve_stream(1, rate=rate, duration=1.0, grids=grids), timeout_s=120)
+    print("serve: warm-up done", file=sys.stderr, flush=True)
+    stream = pdgen.serve_stream(0, rate=rate, duration=seconds, grids=grids)
+    srv.peak_bytes = 0
+    n0 = srv.n_launches
+    reqs, wall = serve.run_stream(srv, stream, timeout_s=seconds * 10 + 60)
+    n_launch = srv.n_launches - n0
+    srv.close()
+    lat = serve.latency_summary([r.latency for r in reqs])
+    by_grid = {str(d): serve.latency_summary([r.latency for r in reqs if r.d == d]) for d in grids}
+    by_kind = {name: serve.latency_summary([r.latency for r in reqs if r.kind == kind])
+               for name, kind in (("distance", serve.DIST), ("assign", serve.ASSIGN))}
+    n_pairs = sum(r.n_pairs(k) for r in reqs)
+    bad = sum(int(np.count_nonzero(r.status & ~8)) for r in reqs)
+    log_path = {str(d): sum(int(np.count_nonzero(r.status & 8)) for r in reqs if r.d == d) for d in grids}
+    print(json.dumps({
+        "metric": "serving latency, arrival to result on the host", "unit": "ms",
+        "p50_ms": lat["p50_ms"], "p99_ms": lat["p99_ms"], "max_ms": lat["max_ms"],
+        "requests": len(reqs), "offered_req_per_s": rate, "duration_s": seconds,
+        "served_req_per_s": len(reqs) / wall, "pairs_per_s": n_pairs / wall, "bad_status_pairs": bad, "log_path_pairs": log_path,
+        "peak_device_bytes": srv.peak_bytes, "launches": n_launch, "by_grid": by_grid, "by_kind": by_kind,
+        "config": {"workload": "Poisson stream, half distances and half k-means assignments (k resident "
+                               "centroids), d uniform in {50, 100, 200}, lognormal(5, 0.7) points",
+                   "k": k, "gamma": GAMMA, "tol": TOL, "slots_per_grid": slots, "max_pairs_per_launch": max_pairs,
+                   "precision": "bf16 contractions, fp32 refinement"},
+        "data": "synthetic"}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -262,6 +312,11 @@ def main():
                     help="run the batch at gamma = 0.1 / n down to 2e-5 and print one line per gamma, then exit")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic record from two --pmc-probe counter runs, then exit")
+    ap.add_argument("--serve", type=float, metavar="SECONDS", default=None,
+                    help="run the serving loop on a Poisson stream for SECONDS and print its latency line, then exit")
+    ap.add_argument("--serve-rate", type=float, default=2000.0, help="offered requests per second (--serve)")
+    ap.add_argument("--serve-slots", type=int, default=2, help="launch slots per grid (--serve)")
+    ap.add_argument("--serve-max-pairs", type=int, default=512, help="pairs per launch at most (--serve)")
     args = ap.parse_args()
     if args.traffic_from:
         write_traffic(*args.traffic_from)
@@ -270,6 +325,9 @@ def main():
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the per-GPU shard is the batch measured at --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.serve is not None:
+        serve_bench(args.serve, rate=args.serve_rate, slots=args.serve_slots, max_pairs=args.serve_max_pairs)
+        return
 
     import torch
     import pdgen

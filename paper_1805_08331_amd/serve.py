@@ -1,0 +1,353 @@
+"""Serving loop: continuous batching of distance and assignment requests.
+
+A request is either a distance between two diagrams (Algorithm 1 on one pair)
+or an assignment of one diagram to the nearest of k centroids held on the
+device (the assignment step of k-means, k pairs).  Requests come at any of
+several grid sizes d.  The loop keeps, per grid, one ``Context``, the
+resident centroid histograms and a fixed number of launch slots; a slot is a
+HIP stream (default priority) with at most one launch in flight.  Each turn
+of ``Server.poll``:
+
+1. retires finished launches: a HIP event per launch is queried without
+   blocking; the launch's outputs were already copied to pinned host memory
+   on its own stream, so its requests get their results and completion time;
+2. admits waiting requests, oldest first, into a free slot of their grid, a
+   request whole (its one pair, or its k pairs), up to a pair cap per launch
+   and within a device-memory budget counted over all launches in flight;
+3. launches the batch on the slot's stream: discretisation of the batch's
+   diagrams, the distance batch and the assignment batch, then the copies
+   back.  Launches in different slots and at different grids run on the
+   device at the same time; requests that arrive meanwhile wait for the next
+   free slot.
+
+Every pair's arithmetic depends only on its own two histograms (the library
+routes and orders pairs by their own supports), so a request's result is the
+same served alone or in a mix.
+
+Latency of a request: from its arrival stamp (host clock) to the turn of the
+loop that sees its result on the host.
+
+Only host logic lives here; every step of the computation runs in the
+library's kernels, through the bindings of this package.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import Context, _lib, kmeans_assign, pd_discretize, sinkhorn_dist_batch
+
+DIST = 0
+ASSIGN = 1
+
+
+@dataclass
+class Request:
+    """One query.  ``diagrams`` holds two point arrays (DIST) or one (ASSIGN),
+    each float32 [n, 2] of (birth, death) in [0, 1]^2."""
+    kind: int
+    d: int
+    diagrams: list
+    t_arrival: float = 0.0
+    rid: int = -1
+    # results, filled when the launch that served the request has finished
+    cost: float | None = None          # DIST: Sinkhorn cost
+    assign: int | None = None          # ASSIGN: nearest centroid
+    dists: np.ndarray | None = None    # ASSIGN: costs to the k centroids
+    status: np.ndarray | None = None   # status word(s) of its pair(s)
+    t_done: float | None = None
+
+    def n_pairs(self, k: int) -> int:
+        return 1 if self.kind == DIST else k
+
+    @property
+    def latency(self) -> float | None:
+        return None if self.t_done is None else self.t_done - self.t_arrival
+
+
+def plan_batch(waiting, k: int, max_pairs: int, budget: int, req_bytes, ws_bytes) -> list:
+    """Requests of one grid for the next launch: the longest prefix of
+    ``waiting`` (oldest first) whose pair count stays within ``max_pairs`` and
+    whose device bytes stay within ``budget``.  The bytes of a prefix are the
+    sum of ``req_bytes(r)`` over its requests plus ``ws_bytes(n_dist,
+    n_assign)``, the workspaces of its two launches.  Requests are taken whole,
+    in arrival order: a request that does not fit ends the batch, so no later
+    request overtakes it."""
+    batch, pairs, rb, nd, na = [], 0, 0, 0, 0
+    for r in waiting:
+        np_ = r.n_pairs(k)
+        nd2, na2 = nd + (r.kind == DIST), na + (r.kind == ASSIGN)
+        rb2 = rb + req_bytes(r)
+        if pairs + np_ > max_pairs or rb2 + ws_bytes(nd2, na2) > budget:
+            break
+        batch.append(r)
+        pairs, rb, nd, na = pairs + np_, rb2, nd2, na2
+    return batch
+
+
+def latency_summary(latencies) -> dict:
+    """p50 / p99 / max of a list of latencies in seconds, in milliseconds
+    (nearest-rank percentiles)."""
+    x = np.sort(np.asarray(latencies, np.float64))
+    if x.size == 0:
+        return {"p50_ms": None, "p99_ms": None, "max_ms": None, "n": 0}
+
+    def rank(q):
+        return float(x[min(x.size - 1, max(0, int(np.ceil(q * x.size)) - 1))] * 1e3)
+
+    return {"p50_ms": rank(0.50), "p99_ms": rank(0.99), "max_ms": float(x[-1] * 1e3), "n": int(x.size)}
+
+
+@dataclass
+class _Launch:
+    reqs: list
+    event: torch.cuda.Event
+    host: dict
+    keep: list            # device tensors that must outlive the launch
+    nbytes: int
+
+
+@dataclass
+class _Grid:
+    ctx: Context
+    centroids: torch.Tensor | None
+    streams: list
+    busy: list
+    waiting: deque = field(default_factory=deque)
+    ws_cache: dict = field(default_factory=dict)
+
+
+class Server:
+    """Continuous-batching server over the library's distance and assignment
+    calls.
+
+    ``centroids`` maps a grid size d to a float32 [k, d, d] device tensor of
+    centroid histograms (k the same for every grid); grids without centroids
+    serve distance requests only.  ``slots`` launches may be in flight per
+    grid, each of at most ``max_pairs`` pairs; ``mem_budget`` caps the device
+    bytes (histograms, workspaces, outputs) of all launches in flight.
+    """
+
+    def __init__(self, grids, gamma: float, centroids=None, slots: int = 2, max_pairs: int = 512,
+                 mem_budget: int = 8 << 30, tol: float = 1e-3, max_iter: int = 5000,
+                 precision="bf16", switch_tol: float = 0.8e-3, device=None, clock=time.perf_counter):
+        if slots < 1 or max_pairs < 1 or mem_budget < 1:
+            raise ValueError("slots, max_pairs and mem_budget must be positive")
+        centroids = centroids or {}
+        ks = {int(c.shape[0]) for c in centroids.values()}
+        if len(ks) > 1:
+            raise ValueError("every grid needs the same number of centroids")
+        self.k = ks.pop() if ks else 0
+        if self.k > max_pairs:
+            raise ValueError("max_pairs must hold one assignment request (k pairs)")
+        self.max_pairs = int(max_pairs)
+        self.mem_budget = int(mem_budget)
+        self.clock = clock
+        self.grids = {}
+        for d in grids:
+            ctx = Context(int(d), gamma, tol=tol, max_iter=max_iter, precision=precision, switch_tol=switch_tol,
+                          device=device)
+            cen = centroids.get(d)
+            if cen is not None and (cen.dtype != torch.float32 or tuple(cen.shape[1:]) != (d, d)
+                                    or cen.device != ctx.device or not cen.is_contiguous()):
+                raise ValueError(f"centroids for d={d} must be a contiguous float32 [k, {d}, {d}] on {ctx.device}")
+            self.grids[int(d)] = _Grid(ctx, cen, [torch.cuda.Stream(device=ctx.device) for _ in range(slots)],
+                                       [None] * slots)
+        self.in_flight_bytes = 0
+        self.peak_bytes = 0      # most device bytes ever in flight at once
+        self.n_launches = 0
+        self.done = []
+        self._next_id = 0
+
+    def close(self):
+        for g in self.grids.values():
+            for s in g.streams:
+                s.synchronize()
+            g.ctx.close()
+
+    # -- submission -------------------------------------------------------
+    def submit(self, req: Request, t_arrival: float | None = None) -> Request:
+        g = self.grids.get(req.d)
+        if g is None:
+            raise ValueError(f"no grid d={req.d}")
+        if req.kind == ASSIGN and g.centroids is None:
+            raise ValueError(f"no centroids at d={req.d}")
+        if len(req.diagrams) != (2 if req.kind == DIST else 1):
+            raise ValueError("a distance needs two diagrams, an assignment one")
+        req.t_arrival = self.clock() if t_arrival is None else t_arrival
+        req.rid = self._next_id
+        self._next_id += 1
+        g.waiting.append(req)
+        return req
+
+    @property
+    def pending(self) -> int:
+        return sum(len(g.waiting) for g in self.grids.values()) + sum(
+            1 for g in self.grids.values() for b in g.busy if b is not None)
+
+    # -- memory accounting --------------------------------------------------
+    def _req_bytes(self, g: _Grid, r: Request) -> int:
+        """Device bytes of one request apart from workspaces: histograms and
+        masses of its diagrams, its points and offsets, its outputs."""
+        d = g.ctx.d
+        nd = len(r.diagrams)
+        b = nd * (d * d * 4 + 8 + 8) + sum(len(x) for x in r.diagrams) * 8
+        return b + (8 + 8 + 4 + 4 + 4 if r.kind == DIST else 4 + self.k * 12)
+
+    def _ws_bytes(self, g: _Grid, n_dist: int, n_asg: int) -> int:
+        """Workspace bytes of a launch with ``n_dist`` distance and ``n_asg``
+        assignment requests (memoised per grid)."""
+        b = 0
+        for op, n in ((_lib.PDSINK_OP_DIST, n_dist), (_lib.PDSINK_OP_KMEANS, n_asg * self.k)):
+            if n:
+                key = (op, n)
+                if key not in g.ws_cache:
+                    g.ws_cache[key] = g.ctx.workspace_bytes(op, n)
+                b += g.ws_cache[key] + 64
+        return b
+
+    def _launch_bytes(self, g: _Grid, reqs) -> int:
+        n_dist = sum(1 for r in reqs if r.kind == DIST)
+        return sum(self._req_bytes(g, r) for r in reqs) + self._ws_bytes(g, n_dist, len(reqs) - n_dist)
+
+    # -- the loop -----------------------------------------------------------
+    def poll(self) -> int:
+        """One turn: retire finished launches, then admit and launch.  Returns
+        the number of requests completed in this turn."""
+        n = self._retire()
+        for d in sorted(self.grids, key=lambda e: self.grids[e].waiting[0].t_arrival
+                        if self.grids[e].waiting else float("inf")):
+            g = self.grids[d]
+            for s in range(len(g.streams)):
+                if not g.waiting:
+                    break
+                if g.busy[s] is not None:
+                    continue
+                budget = self.mem_budget - self.in_flight_bytes
+                batch = plan_batch(g.waiting, self.k, self.max_pairs, budget,
+                                   lambda r, g=g: self._req_bytes(g, r),
+                                   lambda nd, na, g=g: self._ws_bytes(g, nd, na))
+                if not batch:
+                    if self.in_flight_bytes == 0:
+                        raise MemoryError(f"request {g.waiting[0].rid} needs more than the memory budget")
+                    break
+                for _ in batch:
+                    g.waiting.popleft()
+                g.busy[s] = self._launch(g, g.streams[s], batch)
+                self.in_flight_bytes += g.busy[s].nbytes
+                self.peak_bytes = max(self.peak_bytes, self.in_flight_bytes)
+                self.n_launches += 1
+        return n
+
+    def drain(self, timeout_s: float = 60.0):
+        """Poll until nothing waits or runs (raises TimeoutError after
+        ``timeout_s``)."""
+        t0 = time.perf_counter()
+        while self.pending:
+            if self.poll() == 0:
+                time.sleep(2e-5)
+            if time.perf_counter() - t0 > timeout_s:
+                raise TimeoutError(f"{self.pending} requests still pending")
+
+    def _retire(self) -> int:
+        n = 0
+        for g in self.grids.values():
+            for s, L in enumerate(g.busy):
+                if L is None or not L.event.query():
+                    continue
+                now = self.clock()
+                h = L.host
+                di = ai = 0
+                for r in L.reqs:
+                    if r.kind == DIST:
+                        r.cost = float(h["cost"][di])
+                        r.status = h["dstatus"][di:di + 1].copy()
+                        di += 1
+                    else:
+                        r.assign = int(h["assign"][ai])
+                        r.dists = h["adist"][ai].copy()
+                        r.status = h["astatus"][ai].copy()
+                        ai += 1
+                    r.t_done = now
+                    self.done.append(r)
+                n += len(L.reqs)
+                self.in_flight_bytes -= L.nbytes
+                g.busy[s] = None
+        return n
+
+    def _launch(self, g: _Grid, stream, reqs) -> _Launch:
+        ctx, dev = g.ctx, g.ctx.device
+        dreq = [r for r in reqs if r.kind == DIST]
+        areq = [r for r in reqs if r.kind == ASSIGN]
+        keep, host = [], {}
+        nbytes = self._launch_bytes(g, reqs)
+        with torch.cuda.stream(stream):
+            if dreq:
+                hist = _upload(ctx, [x for r in dreq for x in r.diagrams], keep)
+                ia = torch.arange(0, 2 * len(dreq), 2, dtype=torch.int32, device=dev)
+                ib = ia + 1
+                res = sinkhorn_dist_batch(ctx, hist, hist, ia, ib, check_indices=False)
+                keep += [hist, ia, ib, res]
+                host["cost"] = _to_host(res.cost)
+                host["dstatus"] = _to_host(res.status)
+            if areq:
+                hist = _upload(ctx, [r.diagrams[0] for r in areq], keep)
+                assign, dist, status = kmeans_assign(ctx, hist, g.centroids)
+                keep += [hist, assign, dist, status]
+                host["assign"] = _to_host(assign)
+                host["adist"] = _to_host(dist)
+                host["astatus"] = _to_host(status)
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        return _Launch(reqs, ev, {k: v.numpy() for k, v in host.items()}, keep, nbytes)
+
+
+def _upload(ctx: Context, diagrams, keep) -> torch.Tensor:
+    """Histograms of ``diagrams`` on the current stream (CSR points copied from
+    pinned host memory)."""
+    counts = np.array([len(x) for x in diagrams], np.int64)
+    off = np.zeros(len(diagrams) + 1, np.int64)
+    np.cumsum(counts, out=off[1:])
+    pts = np.concatenate([np.asarray(x, np.float32).reshape(-1, 2) for x in diagrams], 0) if off[-1] else \
+        np.zeros((0, 2), np.float32)
+    hp = torch.from_numpy(np.ascontiguousarray(pts)).pin_memory()
+    ho = torch.from_numpy(off).pin_memory()
+    dp = hp.to(ctx.device, non_blocking=True)
+    do = ho.to(ctx.device, non_blocking=True)
+    keep += [hp, ho, dp, do]
+    hist, mass, n_bad = pd_discretize(ctx, dp, do)
+    keep += [mass, n_bad]
+    return hist
+
+
+def _to_host(t: torch.Tensor) -> torch.Tensor:
+    h = torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
+    h.copy_(t, non_blocking=True)
+    return h
+
+
+def run_stream(server: Server, stream, realtime: bool = True, timeout_s: float = 120.0):
+    """Feed ``stream`` (dicts with keys ``t``, ``kind``, ``d``, ``diagrams``,
+    arrival times in seconds) to ``server``.  With ``realtime`` a request is
+    submitted once the clock passes its arrival time and its latency counts
+    from that arrival time; otherwise all are submitted at once.  Returns the
+    requests (with results) and the wall time from the first arrival to the
+    last completion."""
+    reqs = [Request(s["kind"], s["d"], s["diagrams"]) for s in stream]
+    t0 = server.clock()
+    i = 0
+    while i < len(reqs) or server.pending:
+        now = server.clock()
+        while i < len(reqs) and (not realtime or stream[i]["t"] <= now - t0):
+            server.submit(reqs[i], t_arrival=t0 + (stream[i]["t"] if realtime else 0.0))
+            i += 1
+        if server.poll() == 0:
+            time.sleep(2e-5)
+        if server.clock() - t0 > timeout_s:
+            raise TimeoutError(f"{server.pending} requests still pending")
+    t_end = max((r.t_done for r in reqs), default=t0)
+    return reqs, t_end - t0

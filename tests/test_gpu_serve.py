@@ -1,0 +1,123 @@
+"""GPU: the serving loop (continuous batching over the distance and
+assignment calls).  Every request of a mixed stream (grids 50, 100 and 200,
+distances and assignments, lognormal point counts) gets the result it gets
+when served alone, and distances at d = 50 match the converged FP64 oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import pdgen
+from oracle import ground, sinkhorn
+
+pytestmark = pytest.mark.gpu
+
+GRIDS = (50, 100, 200)
+K = 4
+GAMMA = 1e-3
+BF16_RTOL = 1e-3
+MIX_RTOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def pds():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1805_08331_amd as m
+    return m
+
+
+def _centroids(pds):
+    """Resident centroids per grid: histograms of the first K diagrams of a
+    k-means set (the library's own discretisation)."""
+    diags, _ = pdgen.kmeans_set(21, K, n_templates=K, template_size=120)
+    out = {}
+    for d in GRIDS:
+        with pds.Context(d, GAMMA) as ctx:
+            pts, off = pdgen.to_csr(diags)
+            h, _, bad = pds.pd_discretize(ctx, torch.from_numpy(pts).cuda(), torch.from_numpy(off).cuda())
+            torch.cuda.synchronize()
+            assert int(bad.item()) == 0
+            out[d] = h.contiguous()
+    return out
+
+
+def _server(serve, cents, **kw):
+    return serve.Server(GRIDS, GAMMA, centroids=cents, tol=1e-5, max_iter=20000, precision="bf16",
+                        switch_tol=1.5e-3, **kw)
+
+
+def test_serving_mix_equals_alone(pds):
+    from paper_1805_08331_amd import serve
+    cents = _centroids(pds)
+    stream = pdgen.serve_stream(5, rate=2000.0, duration=0.05, grids=GRIDS)
+    assert len(stream) > 50 and {s["kind"] for s in stream} == {0, 1} and {s["d"] for s in stream} == set(GRIDS)
+    print(f"serving mix: {len(stream)} requests", flush=True)
+
+    srv = _server(serve, cents, slots=2, max_pairs=48)
+    mixed, _ = serve.run_stream(srv, stream, realtime=False, timeout_s=100)
+    n_sub = srv._next_id
+    srv.close()
+    assert all(r.t_done is not None for r in mixed) and n_sub == len(stream)
+
+    srv = _server(serve, cents, slots=1, max_pairs=48)
+    alone = []
+    for s in stream:
+        r = srv.submit(serve.Request(s["kind"], s["d"], s["diagrams"]))
+        srv.drain(timeout_s=30)
+        alone.append(r)
+    srv.close()
+
+    same = 0
+    for s, m, a in zip(stream, mixed, alone):
+        assert np.array_equal(m.status, a.status), (m.rid, m.status, a.status)
+        if s["kind"] == serve.DIST:
+            assert np.isfinite(m.cost) and abs(m.cost - a.cost) <= MIX_RTOL * abs(a.cost), (m.rid, m.cost, a.cost)
+            same += m.cost == a.cost
+        else:
+            assert m.assign == a.assign and m.assign == int(np.argmin(m.dists))
+            np.testing.assert_allclose(m.dists, a.dists, rtol=MIX_RTOL)
+            same += bool(np.array_equal(m.dists, a.dists))
+    print(f"bitwise identical alone and in the mix: {same} of {len(stream)}", flush=True)
+
+    # distances at d = 50 against the converged FP64 oracle: the first request
+    # whose oracle run reaches marginal error 1e-7 within 2000 iterations
+    # (at gamma d^2 = 2.5 most need tens of thousands)
+    C = ground.dense_cost(50)
+    checked = 0
+    for s, m in zip(stream, mixed):
+        if s["kind"] != serve.DIST or s["d"] != 50:
+            continue
+        h1, h2 = (ground.discretize(x, 50) for x in s["diagrams"])
+        r = sinkhorn.sinkhorn(h1, h2, GAMMA, tol=1e-7, max_iter=2000, C=C)
+        if r.err > 1e-7:
+            continue
+        assert abs(m.cost - r.cost) <= BF16_RTOL * abs(r.cost), (m.rid, m.cost, r.cost)
+        checked += 1
+        break
+    assert checked == 1
+
+
+def test_serving_memory_budget_and_latency(pds):
+    """A budget that holds the largest 4-request launch of the stream, but not
+    two such launches, still serves every request (launches wait for memory,
+    none is dropped) and is never exceeded; latencies are positive and ordered
+    p50 <= p99 <= max."""
+    from paper_1805_08331_amd import serve
+    stream = pdgen.serve_stream(6, rate=2000.0, duration=0.02, grids=(50,))
+    stream = [s for s in stream if s["kind"] == serve.DIST]
+    assert len(stream) > 8
+    srv = serve.Server((50,), GAMMA, slots=4, max_pairs=4, mem_budget=1 << 40)
+    g = srv.grids[50]
+    win = [srv._launch_bytes(g, [serve.Request(0, 50, s["diagrams"]) for s in stream[i:i + 4]])
+           for i in range(len(stream))]
+    srv.close()
+    budget = int(1.5 * max(win))
+    srv = serve.Server((50,), GAMMA, slots=4, max_pairs=4, mem_budget=budget)
+    reqs, wall = serve.run_stream(srv, stream, realtime=False, timeout_s=60)
+    srv.close()
+    assert srv.in_flight_bytes == 0 and 0 < srv.peak_bytes <= budget
+    assert all(r.cost is not None and np.isfinite(r.cost) for r in reqs)
+    lat = serve.latency_summary([r.latency for r in reqs])
+    assert 0 < lat["p50_ms"] <= lat["p99_ms"] <= lat["max_ms"] and lat["n"] == len(stream)
+    print(f"budget {budget} B, peak {srv.peak_bytes} B, wall {wall * 1e3:.1f} ms, latency {lat}", flush=True)

@@ -1,0 +1,47 @@
+"""Host logic of the serving loop (no GPU): admission of requests into a
+launch and the latency statistics."""
+import numpy as np
+
+from paper_1805_08331_amd.serve import ASSIGN, DIST, Request, latency_summary, plan_batch
+
+
+def _reqs(kinds):
+    pts = np.zeros((3, 2), np.float32)
+    out = []
+    for i, k in enumerate(kinds):
+        r = Request(k, 100, [pts, pts] if k == DIST else [pts])
+        r.rid = i
+        out.append(r)
+    return out
+
+
+def test_plan_batch_pair_cap_in_arrival_order():
+    """k = 4: a distance is one pair, an assignment four.  The cap of 6 pairs
+    admits D, A (5 pairs); the next D would make 6 and fits; the A after it
+    does not, and nothing behind it overtakes."""
+    w = _reqs([DIST, ASSIGN, DIST, ASSIGN, DIST])
+    b = plan_batch(w, 4, 6, 1 << 40, lambda r: 0, lambda nd, na: 0)
+    assert [r.rid for r in b] == [0, 1, 2]
+
+
+def test_plan_batch_memory_budget_counts_workspaces():
+    """Each request costs 10 bytes, each workspace 100 per distance and 1000 per
+    assignment: a budget of 1240 admits D, D, A (30 + 200 + 1000 = 1230)."""
+    w = _reqs([DIST, DIST, ASSIGN, DIST])
+    b = plan_batch(w, 2, 100, 1240, lambda r: 10, lambda nd, na: 100 * nd + 1000 * na)
+    assert [r.rid for r in b] == [0, 1, 2]
+    assert plan_batch(w, 2, 100, 1229, lambda r: 10, lambda nd, na: 100 * nd + 1000 * na) == w[:2]
+
+
+def test_plan_batch_empty_when_first_request_does_not_fit():
+    w = _reqs([ASSIGN, DIST])
+    assert plan_batch(w, 8, 4, 1 << 40, lambda r: 0, lambda nd, na: 0) == []
+    assert plan_batch([], 8, 4, 1 << 40, lambda r: 0, lambda nd, na: 0) == []
+
+
+def test_latency_summary_nearest_rank():
+    lat = np.arange(1, 201) * 1e-3          # 1 .. 200 ms
+    s = latency_summary(lat)
+    assert s["p50_ms"] == 100.0 and s["p99_ms"] == 198.0 and s["max_ms"] == 200.0 and s["n"] == 200
+    assert latency_summary([])["n"] == 0
+    assert latency_summary([0.005])["p99_ms"] == 5.0
