@@ -247,7 +247,7 @@ def gamma_sweep(pts_d, off_d, switch_tol: float):
                 "flagged": int(((st & 6) != 0).sum()), "max_iter": int(((st & 1) != 0).sum())}), flush=True)
 
 
-def serve_bench(seconds: float, rate: float = 2000.0, k: int = 10, slots: int = 2, max_pairs: int = 512):
+def serve_bench(seconds: float, rate: float = 2000.0, k: int = 10, slots: int = 4, max_pairs: int = 512):
     """Serving loop on a Poisson stream: ``rate`` requests/s for ``seconds``
     (after a 1 s warm-up stream), half distances and half assignments to k
     resident centroids, grids 50, 100 and 200, lognormal(5, 0.7) point counts;
@@ -292,7 +292,7 @@ def serve_bench(seconds: float, rate: float = 2000.0, k: int = 10, slots: int = 
         "peak_device_bytes": srv.peak_bytes, "launches": n_launch, "by_grid": by_grid, "by_kind": by_kind,
         "config": {"workload": "Poisson stream, half distances and half k-means assignments (k resident "
                                "centroids), d uniform in {50, 100, 200}, lognormal(5, 0.7) points",
-                   "k": k, "gamma": GAMMA, "tol": TOL, "slots_per_grid": slots, "max_pairs_per_launch": max_pairs,
+                   "k": k, "gamma": GAMMA, "tol": TOL, "slots": slots, "max_pairs_per_launch": max_pairs,
                    "precision": "bf16 contractions, fp32 refinement"},
         "data": "synthetic"}), flush=True)
 
@@ -315,7 +315,7 @@ def main():
     ap.add_argument("--serve", type=float, metavar="SECONDS", default=None,
                     help="run the serving loop on a Poisson stream for SECONDS and print its latency line, then exit")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="offered requests per second (--serve)")
-    ap.add_argument("--serve-slots", type=int, default=2, help="launch slots per grid (--serve)")
+    ap.add_argument("--serve-slots", type=int, default=4, help="launch slots, shared by all grids (--serve)")
     ap.add_argument("--serve-max-pairs", type=int, default=512, help="pairs per launch at most (--serve)")
     args = ap.parse_args()
     if args.traffic_from:

@@ -4,15 +4,19 @@ A request is either a distance between two diagrams (Algorithm 1 on one pair)
 or an assignment of one diagram to the nearest of k centroids held on the
 device (the assignment step of k-means, k pairs).  Requests come at any of
 several grid sizes d.  The loop keeps, per grid, one ``Context``, the
-resident centroid histograms and a fixed number of launch slots; a slot is a
-HIP stream (default priority) with at most one launch in flight.  Each turn
-of ``Server.poll``:
+resident centroid histograms; all grids share a fixed pool of launch slots,
+a slot being a HIP stream (default priority) with at most one launch in
+flight.  The pool is no larger than the hardware queues a process gets (HIP
+maps streams onto four by default): streams beyond that share a queue, and a
+short launch then waits behind a long one on the same queue.  Each turn of
+``Server.poll``:
 
 1. retires finished launches: a HIP event per launch is queried without
    blocking; the launch's outputs were already copied to pinned host memory
    on its own stream, so its requests get their results and completion time;
-2. admits waiting requests, oldest first, into a free slot of their grid, a
-   request whole (its one pair, or its k pairs), up to a pair cap per launch
+2. gives each free slot to the grid whose oldest waiting request is the
+   oldest, and admits that grid's waiting requests, oldest first, a request
+   whole (its one pair, or its k pairs), up to a pair cap per launch
    and within a device-memory budget counted over all launches in flight;
 3. launches the batch on the slot's stream: discretisation of the batch's
    diagrams, the distance batch and the assignment batch, then the copies
@@ -115,8 +119,6 @@ class _Launch:
 class _Grid:
     ctx: Context
     centroids: torch.Tensor | None
-    streams: list
-    busy: list
     waiting: deque = field(default_factory=deque)
     ws_cache: dict = field(default_factory=dict)
 
@@ -127,12 +129,12 @@ class Server:
 
     ``centroids`` maps a grid size d to a float32 [k, d, d] device tensor of
     centroid histograms (k the same for every grid); grids without centroids
-    serve distance requests only.  ``slots`` launches may be in flight per
-    grid, each of at most ``max_pairs`` pairs; ``mem_budget`` caps the device
+    serve distance requests only.  ``slots`` launches (one per slot, all
+    grids together) may be in flight, each of at most ``max_pairs`` pairs; ``mem_budget`` caps the device
     bytes (histograms, workspaces, outputs) of all launches in flight.
     """
 
-    def __init__(self, grids, gamma: float, centroids=None, slots: int = 2, max_pairs: int = 512,
+    def __init__(self, grids, gamma: float, centroids=None, slots: int = 4, max_pairs: int = 512,
                  mem_budget: int = 8 << 30, tol: float = 1e-3, max_iter: int = 5000,
                  precision="bf16", switch_tol: float = 0.8e-3, device=None, clock=time.perf_counter):
         if slots < 1 or max_pairs < 1 or mem_budget < 1:
@@ -155,8 +157,10 @@ class Server:
             if cen is not None and (cen.dtype != torch.float32 or tuple(cen.shape[1:]) != (d, d)
                                     or cen.device != ctx.device or not cen.is_contiguous()):
                 raise ValueError(f"centroids for d={d} must be a contiguous float32 [k, {d}, {d}] on {ctx.device}")
-            self.grids[int(d)] = _Grid(ctx, cen, [torch.cuda.Stream(device=ctx.device) for _ in range(slots)],
-                                       [None] * slots)
+            self.grids[int(d)] = _Grid(ctx, cen)
+        dev = next(iter(self.grids.values())).ctx.device
+        self.streams = [torch.cuda.Stream(device=dev) for _ in range(slots)]
+        self.busy = [None] * slots      # per slot: (grid, launch) in flight, or None
         self.in_flight_bytes = 0
         self.peak_bytes = 0      # most device bytes ever in flight at once
         self.n_launches = 0
@@ -164,9 +168,9 @@ class Server:
         self._next_id = 0
 
     def close(self):
+        for s in self.streams:
+            s.synchronize()
         for g in self.grids.values():
-            for s in g.streams:
-                s.synchronize()
             g.ctx.close()
 
     # -- submission -------------------------------------------------------
@@ -187,7 +191,7 @@ class Server:
     @property
     def pending(self) -> int:
         return sum(len(g.waiting) for g in self.grids.values()) + sum(
-            1 for g in self.grids.values() for b in g.busy if b is not None)
+            len(b[1].reqs) for b in self.busy if b is not None)
 
     # -- memory accounting --------------------------------------------------
     def _req_bytes(self, g: _Grid, r: Request) -> int:
@@ -219,28 +223,28 @@ class Server:
         """One turn: retire finished launches, then admit and launch.  Returns
         the number of requests completed in this turn."""
         n = self._retire()
-        for d in sorted(self.grids, key=lambda e: self.grids[e].waiting[0].t_arrival
-                        if self.grids[e].waiting else float("inf")):
-            g = self.grids[d]
-            for s in range(len(g.streams)):
-                if not g.waiting:
-                    break
-                if g.busy[s] is not None:
-                    continue
-                budget = self.mem_budget - self.in_flight_bytes
-                batch = plan_batch(g.waiting, self.k, self.max_pairs, budget,
-                                   lambda r, g=g: self._req_bytes(g, r),
-                                   lambda nd, na, g=g: self._ws_bytes(g, nd, na))
-                if not batch:
-                    if self.in_flight_bytes == 0:
-                        raise MemoryError(f"request {g.waiting[0].rid} needs more than the memory budget")
-                    break
-                for _ in batch:
-                    g.waiting.popleft()
-                g.busy[s] = self._launch(g, g.streams[s], batch)
-                self.in_flight_bytes += g.busy[s].nbytes
-                self.peak_bytes = max(self.peak_bytes, self.in_flight_bytes)
-                self.n_launches += 1
+        for s in range(len(self.streams)):
+            if self.busy[s] is not None:
+                continue
+            ready = [g for g in self.grids.values() if g.waiting]
+            if not ready:
+                break
+            g = min(ready, key=lambda e: e.waiting[0].t_arrival)
+            budget = self.mem_budget - self.in_flight_bytes
+            batch = plan_batch(g.waiting, self.k, self.max_pairs, budget,
+                               lambda r, g=g: self._req_bytes(g, r),
+                               lambda nd, na, g=g: self._ws_bytes(g, nd, na))
+            if not batch:
+                if self.in_flight_bytes == 0:
+                    raise MemoryError(f"request {g.waiting[0].rid} needs more than the memory budget")
+                break
+            for _ in batch:
+                g.waiting.popleft()
+            L = self._launch(g, self.streams[s], batch)
+            self.busy[s] = (g, L)
+            self.in_flight_bytes += L.nbytes
+            self.peak_bytes = max(self.peak_bytes, self.in_flight_bytes)
+            self.n_launches += 1
         return n
 
     def drain(self, timeout_s: float = 60.0):
@@ -255,28 +259,28 @@ class Server:
 
     def _retire(self) -> int:
         n = 0
-        for g in self.grids.values():
-            for s, L in enumerate(g.busy):
-                if L is None or not L.event.query():
-                    continue
-                now = self.clock()
-                h = L.host
-                di = ai = 0
-                for r in L.reqs:
-                    if r.kind == DIST:
-                        r.cost = float(h["cost"][di])
-                        r.status = h["dstatus"][di:di + 1].copy()
-                        di += 1
-                    else:
-                        r.assign = int(h["assign"][ai])
-                        r.dists = h["adist"][ai].copy()
-                        r.status = h["astatus"][ai].copy()
-                        ai += 1
-                    r.t_done = now
-                    self.done.append(r)
-                n += len(L.reqs)
-                self.in_flight_bytes -= L.nbytes
-                g.busy[s] = None
+        for s, b in enumerate(self.busy):
+            if b is None or not b[1].event.query():
+                continue
+            L = b[1]
+            now = self.clock()
+            h = L.host
+            di = ai = 0
+            for r in L.reqs:
+                if r.kind == DIST:
+                    r.cost = float(h["cost"][di])
+                    r.status = h["dstatus"][di:di + 1].copy()
+                    di += 1
+                else:
+                    r.assign = int(h["assign"][ai])
+                    r.dists = h["adist"][ai].copy()
+                    r.status = h["astatus"][ai].copy()
+                    ai += 1
+                r.t_done = now
+                self.done.append(r)
+            n += len(L.reqs)
+            self.in_flight_bytes -= L.nbytes
+            self.busy[s] = None
         return n
 
     def _launch(self, g: _Grid, stream, reqs) -> _Launch:
