@@ -247,7 +247,8 @@ def gamma_sweep(pts_d, off_d, switch_tol: float):
                 "flagged": int(((st & 6) != 0).sum()), "max_iter": int(((st & 1) != 0).sum())}), flush=True)
 
 
-def serve_bench(seconds: float, rate: float = 2000.0, k: int = 10, slots: int = 4, max_pairs: int = 512):
+def serve_bench(seconds: float, rate: float = 2000.0, k: int = 10, slots: int = 16, max_pairs: int = 512,
+                mem_budget: int = 64 << 30):
     """Serving loop on a Poisson stream: ``rate`` requests/s for ``seconds``
     (after a 1 s warm-up stream), half distances and half assignments to k
     resident centroids, grids 50, 100 and 200, lognormal(5, 0.7) point counts;
@@ -267,8 +268,8 @@ def serve_bench(seconds: float, rate: float = 2000.0, k: int = 10, slots: int = 
             h, _, _ = pds.pd_discretize(ctx, torch.from_numpy(pts).cuda(), torch.from_numpy(off).cuda())
             torch.cuda.synchronize()
             cents[d] = h.contiguous()
-    srv = serve.Server(grids, GAMMA, centroids=cents, slots=slots, max_pairs=max_pairs, tol=TOL, max_iter=5000,
-                       precision="bf16", switch_tol=0.8e-3)
+    srv = serve.Server(grids, GAMMA, centroids=cents, slots=slots, max_pairs=max_pairs, mem_budget=mem_budget,
+                       tol=TOL, max_iter=5000, precision="bf16", switch_tol=0.8e-3)
     serve.run_stream(srv, pdgen.serve_stream(1, rate=rate, duration=1.0, grids=grids), timeout_s=120)
     print("serve: warm-up done", file=sys.stderr, flush=True)
     stream = pdgen.serve_stream(0, rate=rate, duration=seconds, grids=grids)
@@ -292,7 +293,8 @@ def serve_bench(seconds: float, rate: float = 2000.0, k: int = 10, slots: int = 
         "peak_device_bytes": srv.peak_bytes, "launches": n_launch, "by_grid": by_grid, "by_kind": by_kind,
         "config": {"workload": "Poisson stream, half distances and half k-means assignments (k resident "
                                "centroids), d uniform in {50, 100, 200}, lognormal(5, 0.7) points",
-                   "k": k, "gamma": GAMMA, "tol": TOL, "slots": slots, "max_pairs_per_launch": max_pairs,
+                   "k": k, "gamma": GAMMA, "tol": TOL, "slots": slots, "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"),
+                   "max_pairs_per_launch": max_pairs, "mem_budget_bytes": mem_budget,
                    "precision": "bf16 contractions, fp32 refinement"},
         "data": "synthetic"}), flush=True)
 
@@ -315,7 +317,9 @@ def main():
     ap.add_argument("--serve", type=float, metavar="SECONDS", default=None,
                     help="run the serving loop on a Poisson stream for SECONDS and print its latency line, then exit")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="offered requests per second (--serve)")
-    ap.add_argument("--serve-slots", type=int, default=4, help="launch slots, shared by all grids (--serve)")
+    ap.add_argument("--serve-slots", type=int, default=16, help="launch slots, shared by all grids (--serve)")
+    ap.add_argument("--serve-hw-queues", type=int, default=16,
+                    help="hardware queues of the process (GPU_MAX_HW_QUEUES, set before HIP starts; --serve)")
     ap.add_argument("--serve-max-pairs", type=int, default=512, help="pairs per launch at most (--serve)")
     args = ap.parse_args()
     if args.traffic_from:
@@ -326,6 +330,11 @@ def main():
               "(the per-GPU shard is the batch measured at --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.serve is not None:
+        if not 1 <= args.serve_hw_queues <= 16:
+            print("--serve-hw-queues must be in 1..16", file=sys.stderr)
+            sys.exit(2)
+        # read by the HIP runtime when it starts (torch is not imported yet)
+        os.environ["GPU_MAX_HW_QUEUES"] = str(args.serve_hw_queues)
         serve_bench(args.serve, rate=args.serve_rate, slots=args.serve_slots, max_pairs=args.serve_max_pairs)
         return
 

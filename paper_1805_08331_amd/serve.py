@@ -6,9 +6,12 @@ device (the assignment step of k-means, k pairs).  Requests come at any of
 several grid sizes d.  The loop keeps, per grid, one ``Context``, the
 resident centroid histograms; all grids share a fixed pool of launch slots,
 a slot being a HIP stream (default priority) with at most one launch in
-flight.  The pool is no larger than the hardware queues a process gets (HIP
-maps streams onto four by default): streams beyond that share a queue, and a
-short launch then waits behind a long one on the same queue.  Each turn of
+flight.  The pool should be no larger than the hardware queues the process
+gets (``GPU_MAX_HW_QUEUES``, read when the HIP runtime starts; four by
+default): streams beyond that share a queue, and a short launch then waits
+behind a long one on the same queue.  More queues let more launches overlap:
+a launch retires only when its slowest pair is done, and while it waits the
+other slots keep the chip busy.  Each turn of
 ``Server.poll``:
 
 1. retires finished launches: a HIP event per launch is queried without
