@@ -314,6 +314,8 @@ def main():
                     help="run the batch at gamma = 0.1 / n down to 2e-5 and print one line per gamma, then exit")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic record from two --pmc-probe counter runs, then exit")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the benchmark batch at several BF16 -> FP32 switch points, print the choice, then exit")
     ap.add_argument("--serve", type=float, metavar="SECONDS", default=None,
                     help="run the serving loop on a Poisson stream for SECONDS and print its latency line, then exit")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="offered requests per second (--serve)")
@@ -351,6 +353,18 @@ def main():
         return
     if args.gamma_sweep:
         gamma_sweep(pts_d, off_d, args.switch_tol)
+        return
+    if args.autotune:
+        import paper_1805_08331_amd as pds
+        from paper_1805_08331_amd import autotune
+        with pds.Context(D, GAMMA) as ctx:
+            hist, _, _ = pds.pd_discretize(ctx, pts_d, off_d)
+        ia = torch.arange(0, NPAIRS, dtype=torch.int32, device=hist.device)
+        r = autotune.tune_switch_tol(hist, hist, ia, ia + NPAIRS, D, GAMMA, TOL, reps=5)
+        print(json.dumps({"autotune": "switch_tol", "workload": f"{NPAIRS} pairs, d={D}, gamma={GAMMA}, tol={TOL}",
+                          "switch_tol": r["switch_tol"],
+                          "median_ms": {f"{k:.3g}": float(np.median(v)) for k, v in r["ms"].items()},
+                          "iters_bf16_fp32": {f"{k:.3g}": v for k, v in r["iters"].items()}}), flush=True)
         return
 
     res = {}

@@ -121,3 +121,29 @@ def test_serving_memory_budget_and_latency(pds):
     lat = serve.latency_summary([r.latency for r in reqs])
     assert 0 < lat["p50_ms"] <= lat["p99_ms"] <= lat["max_ms"] and lat["n"] == len(stream)
     print(f"budget {budget} B, peak {srv.peak_bytes} B, wall {wall * 1e3:.1f} ms, latency {lat}", flush=True)
+
+
+def test_autotune_switch_point(pds):
+    """The tuner times each candidate switch point on the caller's pairs and
+    returns one of them; every candidate meets the stopping rule (FP32
+    iterations decide it), and the costs at the chosen point are those of a
+    plain call with that switch point."""
+    from paper_1805_08331_amd import autotune
+    d, g, tol = 50, 1e-3, 1e-3
+    D1s, D2s = pdgen.pairs_batch(9, 64, 20, 200)
+    with pds.Context(d, g) as ctx:
+        pts, off = pdgen.to_csr(list(D1s) + list(D2s))
+        hist, _, bad = pds.pd_discretize(ctx, torch.from_numpy(pts).cuda(), torch.from_numpy(off).cuda())
+        torch.cuda.synchronize()
+        assert int(bad.item()) == 0
+    ia = torch.arange(0, 64, dtype=torch.int32, device="cuda")
+    ib = ia + 64
+    r = autotune.tune_switch_tol(hist, hist, ia, ib, d, g, tol, fractions=(0.5, 1.0), reps=2)
+    assert r["switch_tol"] in (0.5e-3, 1e-3) and set(r["ms"]) == {0.5e-3, 1e-3}
+    assert all(len(v) == 2 and min(v) > 0 for v in r["ms"].values())
+    assert all(it[0] > 0 for it in r["iters"].values())
+    with pds.Context(d, g, tol=tol, max_iter=5000, precision="bf16", switch_tol=r["switch_tol"]) as ctx:
+        out = pds.sinkhorn_dist_batch(ctx, hist, hist, ia, ib)
+        torch.cuda.synchronize()
+    assert np.all(out.status.cpu().numpy() == 0) and np.all(out.err.cpu().numpy() <= tol)
+    print(f"autotune: {r}", flush=True)

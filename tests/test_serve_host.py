@@ -45,3 +45,11 @@ def test_latency_summary_nearest_rank():
     assert s["p50_ms"] == 100.0 and s["p99_ms"] == 198.0 and s["max_ms"] == 200.0 and s["n"] == 200
     assert latency_summary([])["n"] == 0
     assert latency_summary([0.005])["p99_ms"] == 5.0
+
+
+def test_autotune_pick_fastest_median_and_ties():
+    """The tuner keeps the candidate with the smallest median time; on a tie
+    the larger switch point wins."""
+    from paper_1805_08331_amd.autotune import pick_fastest
+    assert pick_fastest({5e-4: [3.0, 9.0, 3.1], 8e-4: [2.9, 3.0, 30.0], 1e-3: [3.2, 3.2, 3.2]}) == 8e-4
+    assert pick_fastest({5e-4: [2.0], 8e-4: [2.0]}) == 8e-4
