@@ -243,7 +243,11 @@ class Server:
                 break
             for _ in batch:
                 g.waiting.popleft()
-            L = self._launch(g, self.streams[s], batch)
+            try:
+                L = self._launch(g, self.streams[s], batch)
+            except Exception:
+                g.waiting.extendleft(reversed(batch))     # back at the head, in order
+                raise
             self.busy[s] = (g, L)
             self.in_flight_bytes += L.nbytes
             self.peak_bytes = max(self.peak_bytes, self.in_flight_bytes)

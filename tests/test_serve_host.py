@@ -53,3 +53,39 @@ def test_autotune_pick_fastest_median_and_ties():
     from paper_1805_08331_amd.autotune import pick_fastest
     assert pick_fastest({5e-4: [3.0, 9.0, 3.1], 8e-4: [2.9, 3.0, 30.0], 1e-3: [3.2, 3.2, 3.2]}) == 8e-4
     assert pick_fastest({5e-4: [2.0], 8e-4: [2.0]}) == 8e-4
+
+
+def test_failed_launch_puts_requests_back_in_order():
+    """A launch that raises leaves its requests at the head of the queue, in
+    arrival order (exercised with a stand-in server: no GPU)."""
+    from collections import deque
+    from paper_1805_08331_amd import serve
+
+    class _G:
+        def __init__(self, reqs):
+            self.waiting = deque(reqs)
+            self.ws_cache = {}
+
+    srv = serve.Server.__new__(serve.Server)
+    w = _reqs([DIST, DIST, DIST])
+    g = _G(w)
+    srv.grids = {100: g}
+    srv.streams = [None]
+    srv.busy = [None]
+    srv.k, srv.max_pairs, srv.mem_budget = 1, 2, 1 << 40
+    srv.in_flight_bytes = srv.peak_bytes = srv.n_launches = 0
+    srv.done = []
+    srv._req_bytes = lambda g, r: 0
+    srv._ws_bytes = lambda g, nd, na: 0
+
+    def boom(g, stream, batch):
+        raise RuntimeError("launch failed")
+
+    srv._launch = boom
+    try:
+        srv.poll()
+    except RuntimeError:
+        pass
+    else:
+        raise AssertionError("the launch error was swallowed")
+    assert [r.rid for r in g.waiting] == [0, 1, 2] and srv.in_flight_bytes == 0
