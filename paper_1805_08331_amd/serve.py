@@ -142,6 +142,8 @@ class Server:
                  precision="bf16", switch_tol: float = 0.8e-3, device=None, clock=time.perf_counter):
         if slots < 1 or max_pairs < 1 or mem_budget < 1:
             raise ValueError("slots, max_pairs and mem_budget must be positive")
+        if not grids:
+            raise ValueError("at least one grid is needed")
         centroids = centroids or {}
         ks = {int(c.shape[0]) for c in centroids.values()}
         if len(ks) > 1:
@@ -185,6 +187,7 @@ class Server:
             raise ValueError(f"no centroids at d={req.d}")
         if len(req.diagrams) != (2 if req.kind == DIST else 1):
             raise ValueError("a distance needs two diagrams, an assignment one")
+        req.diagrams = [_checked_points(x) for x in req.diagrams]
         req.t_arrival = self.clock() if t_arrival is None else t_arrival
         req.rid = self._next_id
         self._next_id += 1
@@ -315,6 +318,21 @@ class Server:
             ev = torch.cuda.Event()
             ev.record(stream)
         return _Launch(reqs, ev, {k: v.numpy() for k, v in host.items()}, keep, nbytes)
+
+
+def _checked_points(x) -> np.ndarray:
+    """A diagram as float32 [n, 2].  Raises ValueError for a point that the
+    discretisation would drop (outside [0, 1]^2, non-finite, or birth >
+    death), so that no request is served without part of its diagram."""
+    a = np.asarray(x, dtype=np.float32)
+    if a.size % 2:
+        raise ValueError("a diagram is an array of (birth, death) pairs")
+    a = np.ascontiguousarray(a.reshape(-1, 2))
+    with np.errstate(invalid="ignore"):
+        bad = ~np.isfinite(a).all(axis=1) | (a < 0).any(axis=1) | (a > 1).any(axis=1) | (a[:, 0] > a[:, 1])
+    if bad.any():
+        raise ValueError(f"{int(bad.sum())} points outside [0, 1]^2, non-finite or with birth > death")
+    return a
 
 
 def _upload(ctx: Context, diagrams, keep) -> torch.Tensor:

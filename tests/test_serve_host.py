@@ -89,3 +89,32 @@ def test_failed_launch_puts_requests_back_in_order():
     else:
         raise AssertionError("the launch error was swallowed")
     assert [r.rid for r in g.waiting] == [0, 1, 2] and srv.in_flight_bytes == 0
+
+
+def test_submit_rejects_points_the_discretisation_would_drop():
+    """Points outside [0, 1]^2, non-finite, or with birth > death are refused at
+    submission (the library would drop them silently); valid diagrams are
+    stored as float32 [n, 2]."""
+    from paper_1805_08331_amd import serve
+
+    class _G:
+        centroids = object()
+
+        def __init__(self):
+            from collections import deque
+            self.waiting = deque()
+
+    srv = serve.Server.__new__(serve.Server)
+    srv.grids = {100: _G()}
+    srv.clock = lambda: 1.0
+    srv._next_id = 0
+    ok = srv.submit(serve.Request(ASSIGN, 100, [[0.1, 0.5, 0.0, 1.0]]))
+    assert ok.diagrams[0].dtype == np.float32 and ok.diagrams[0].shape == (2, 2) and ok.rid == 0
+    for bad in ([[0.5, 0.4]], [[0.1, 1.5]], [[-0.1, 0.2]], [[np.nan, 0.3]], [[0.1, 0.2, 0.3]]):
+        try:
+            srv.submit(serve.Request(ASSIGN, 100, [np.asarray(bad, np.float64)]))
+        except ValueError:
+            pass
+        else:
+            raise AssertionError(bad)
+    assert len(srv.grids[100].waiting) == 1
