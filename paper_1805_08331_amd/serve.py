@@ -188,6 +188,10 @@ class Server:
         if len(req.diagrams) != (2 if req.kind == DIST else 1):
             raise ValueError("a distance needs two diagrams, an assignment one")
         req.diagrams = [_checked_points(x) for x in req.diagrams]
+        if self._launch_bytes(g, [req]) > self.mem_budget:
+            # it could never be admitted, and at the head of its queue it would block the grid
+            raise ValueError(f"request needs {self._launch_bytes(g, [req])} device bytes, more than the "
+                             f"memory budget of {self.mem_budget}")
         req.t_arrival = self.clock() if t_arrival is None else t_arrival
         req.rid = self._next_id
         self._next_id += 1

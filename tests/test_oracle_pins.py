@@ -375,3 +375,127 @@ def test_kmeans_assign_separated_clusters():
     labels, dist, _ = kmeans.assign(near + far, cents, 1e-2, tol=1e-6)
     assert list(labels) == [0, 0, 1]
     assert dist[0, 0] == dist[0, 2]          # identical centroids: the tie goes to index 0
+
+
+def test_barycenter_step_is_finite_difference_gradient():
+    """Algorithm 2's update z <- z exp(-lambda grad) with grad the derivative of
+    the mean regularised objective (1/N) sum_i L^gamma(z + R a_i, a_i + R z)
+    (Proposition 5; gradient averaged over the diagrams).  The step of
+    ``barycenter`` is compared with central differences of that objective,
+    evaluated by ``entropic_objective`` of converged plans, which involves no
+    gradient formula: a dropped diagonal-bin term, a wrong sign or a sum in
+    place of the mean each move z by more than 20 %."""
+    d, gamma, lam = 5, 0.05, 3.0
+    C = ground.dense_cost(d)
+    rng = np.random.default_rng(3)
+    hists = [np.triu(rng.random((d, d)) < 0.35).astype(float) for _ in range(2)]
+    hists[0][0, 2] += 1
+    hists[1][3, 4] += 2
+    z0 = barycenter.uniform_init(d, float(np.mean([h.sum() for h in hists])))
+    r = barycenter.barycenter(hists, gamma, lam=lam, tol=1e-13, max_inner=500000, max_outer=2,
+                              energy_rtol=0.0, z0=z0, C=C)
+    assert r.outer == 2
+
+    def L_mean(z):
+        tot = 0.0
+        for h in hists:
+            a, b = ground.marginals(z, h)
+            s = sinkhorn.solve(a, b, C, gamma, tol=1e-14, max_iter=500000)
+            tot += sinkhorn.entropic_objective(sinkhorn.plan(s, C, gamma), C, gamma)
+        return tot / len(hists)
+
+    eps = 1e-6
+    for i in range(d):
+        for j in range(d):
+            if j < i:
+                assert r.z[i, j] == 0.0          # the multiplicative step keeps the support
+                continue
+            zp, zm = z0.copy(), z0.copy()
+            zp[i, j] += eps
+            zm[i, j] -= eps
+            g = (L_mean(zp) - L_mean(zm)) / (2 * eps)
+            assert math.isclose(r.z[i, j], z0[i, j] * math.exp(-lam * g), rel_tol=1e-7), (i, j)
+
+
+def test_barycenter_single_diagram_concentrates_as_gamma_falls():
+    """N = 1: the barycenter of one diagram is the diagram itself, so as gamma
+    falls the smoothed barycenter puts more of its mass on the diagram's cells
+    and its total mass approaches the diagram's (the diagonal-bin term of the
+    gradient is what sets the mass)."""
+    d = 8
+    C = ground.dense_cost(d)
+    h = ground.discretize(np.array([[1 / 8, 5 / 8], [2 / 8, 6 / 8]], np.float32), d)
+    on, mass = [], []
+    for g in (8e-3, 4e-3, 2e-3):
+        r = barycenter.barycenter([h], g, lam=2.0, tol=1e-8, max_inner=200000, max_outer=80, energy_rtol=1e-7, C=C)
+        on.append(float((r.z * (h > 0)).sum() / r.z.sum()))
+        mass.append(float(r.z.sum()))
+    assert on[0] < on[1] < on[2]
+    assert mass[0] > mass[1] > mass[2] > h.sum()
+
+
+def _two_families(d, n_each=3, seed=1):
+    rng = np.random.default_rng(seed)
+
+    def fam(center):
+        out = []
+        for _ in range(n_each):
+            p = np.clip(np.array(center) + rng.normal(0, 0.02, (3, 2)), 0, 1)
+            p[:, 1] = np.maximum(p[:, 1], p[:, 0])
+            out.append(ground.discretize(p.astype(np.float32), d))
+        return out
+
+    return fam([0.1, 0.25]) + fam([0.55, 0.95])
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_lloyd_separates_two_families(seed):
+    """Section 5 k-means on diagrams around two far-apart templates: the final
+    partition is the two families, whatever the seeded initial centroids
+    (seed 0 draws both from the same family).  Once the centroids are
+    barycenters (every round after the first) the objective never rises, and
+    it stays fixed once the partition does (same members, same barycenter)."""
+    d, g = 10, 1e-2
+    hists = _two_families(d)
+    cents, labels, hist = kmeans.lloyd(hists, 2, 4, g, tol=1e-6, seed=seed, max_outer=8)
+    assert len(set(labels[:3])) == 1 and len(set(labels[3:])) == 1 and labels[0] != labels[3]
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(hist[1:], hist[2:]))
+    assert hist[-1] == hist[-2]
+
+
+def test_lloyd_empty_cluster_keeps_centroid():
+    """Section 5 readings: ties go to the lowest centroid index, so of two
+    identical initial centroids the second gets no member, and a cluster
+    without members keeps its centroid."""
+    d, g = 10, 1e-2
+    hists = _two_families(d)
+    hists = hists + [hists[0].copy()]          # diagram 6 duplicates diagram 0
+    init = np.random.default_rng(11).choice(len(hists), size=3, replace=False)
+    assert sorted(init.tolist()) == [0, 5, 6]
+    c_dup = int(np.flatnonzero(init == 6)[0])
+    c_orig = int(np.flatnonzero(init == 0)[0])
+    assert c_orig < c_dup
+    cents, labels, _ = kmeans.lloyd(hists, 3, 1, g, tol=1e-6, seed=11, max_outer=4)
+    assert c_dup not in labels.tolist()
+    np.testing.assert_array_equal(cents[c_dup], hists[6])
+
+
+def test_lloyd_singleton_clusters():
+    """k = N: every diagram starts as its own centroid, so the first
+    assignment is a bijection and the first objective is the sum of the
+    self-distances S(D, D) (each within the entropic bound 2 gamma m log m of
+    the exact value 0)."""
+    d, g = 10, 1e-2
+    pts = ([[0.05, 0.25], [0.1, 0.3]], [[0.15, 0.55]], [[0.5, 0.95], [0.62, 0.9]], [[0.3, 0.45], [0.72, 0.85]])
+    hists = [ground.discretize(np.array(p, np.float32), d) for p in pts]
+    N = len(hists)
+    cents, labels, hist = kmeans.lloyd(hists, N, 1, g, tol=1e-6, seed=2, max_outer=2)
+    assert sorted(labels.tolist()) == list(range(N))
+    C = ground.dense_cost(d)
+    self_d = []
+    for h in hists:
+        a, b = ground.marginals(h, h)
+        self_d.append(sinkhorn.solve(a, b, C, g, tol=1e-6, max_iter=1000).cost)
+        m = 2 * h.sum()
+        assert 0.0 <= self_d[-1] <= 2 * g * m * math.log(m)
+    assert math.isclose(hist[0], sum(self_d), rel_tol=1e-12)

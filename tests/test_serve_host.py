@@ -108,6 +108,8 @@ def test_submit_rejects_points_the_discretisation_would_drop():
     srv.grids = {100: _G()}
     srv.clock = lambda: 1.0
     srv._next_id = 0
+    srv.mem_budget = 1 << 40
+    srv._launch_bytes = lambda g, reqs: 0
     ok = srv.submit(serve.Request(ASSIGN, 100, [[0.1, 0.5, 0.0, 1.0]]))
     assert ok.diagrams[0].dtype == np.float32 and ok.diagrams[0].shape == (2, 2) and ok.rid == 0
     for bad in ([[0.5, 0.4]], [[0.1, 1.5]], [[-0.1, 0.2]], [[np.nan, 0.3]], [[0.1, 0.2, 0.3]]):
@@ -118,3 +120,32 @@ def test_submit_rejects_points_the_discretisation_would_drop():
         else:
             raise AssertionError(bad)
     assert len(srv.grids[100].waiting) == 1
+
+
+def test_submit_rejects_request_beyond_memory_budget():
+    """A request that alone needs more device memory than the budget could
+    never be admitted; it is refused at submission instead of blocking the
+    head of its grid's queue."""
+    from paper_1805_08331_amd import serve
+
+    class _G:
+        centroids = object()
+
+        def __init__(self):
+            from collections import deque
+            self.waiting = deque()
+
+    srv = serve.Server.__new__(serve.Server)
+    srv.grids = {100: _G()}
+    srv.clock = lambda: 1.0
+    srv._next_id = 0
+    srv.mem_budget = 1000
+    srv._launch_bytes = lambda g, reqs: 500 * sum(len(r.diagrams[0]) for r in reqs)
+    srv.submit(serve.Request(ASSIGN, 100, [[0.1, 0.5, 0.2, 0.6]]))
+    try:
+        srv.submit(serve.Request(ASSIGN, 100, [[0.1, 0.5, 0.2, 0.6, 0.3, 0.7]]))
+    except ValueError:
+        pass
+    else:
+        raise AssertionError("oversized request accepted")
+    assert len(srv.grids[100].waiting) == 1 and srv._next_id == 1
