@@ -125,9 +125,12 @@ int pd_discretize(pdsink_ctx* ctx, const float* pts, const int64_t* offsets, int
  * side) run again with their lists in the workspace, from the same launch
  * sequence.  A pair whose scaled solve ends NONFINITE or RANGE (a kernel so
  * sharp that one grid step costs tens of octaves, gamma d^2 well below 1) is
- * solved again from the start by the same iteration in FP64 log-sum-exp form
- * over the two supports (up to 1024 cells per side; larger pairs keep their
- * flags): status PDSINK_ST_LOG_PATH, iterations reported in the FP32 slot. */
+ * solved again from the start by the same iteration in log-sum-exp form over
+ * the two supports (up to 1024 cells per side; larger pairs keep their
+ * flags): maxima, logarithms, sums and the cost in FP64, the exponentials
+ * FP32-accurate (exponent split in FP64, hardware base-2 exponential), so the
+ * result matches the FP64 log-domain iteration to the FP32 tolerance.  Status
+ * PDSINK_ST_LOG_PATH, iterations reported in the FP32 slot. */
 int sinkhorn_dist_batch(pdsink_ctx* ctx, int64_t n_pairs,
                         const float* hist_a, const float* hist_b,
                         const int32_t* ia, const int32_t* ib,
@@ -169,7 +172,11 @@ int sinkhorn_dist_bounds_batch(pdsink_ctx* ctx, int64_t n_pairs,
  *            total mass = mean diagram mass; on return, z_t.
  *   energy   (host)   double out, E_t;  outer (host) int32 out, t
  * This call synchronises `stream` between outer steps (the stopping test is on
- * the host).  n_diag >= 1. */
+ * the host).  n_diag >= 1.  PDSINK_ERANGE when an inner solve ends with
+ * PDSINK_ST_NONFINITE or PDSINK_ST_RANGE (its iterates left the scaled
+ * representation, gamma d^2 of order 1 or below): the energy and the step
+ * would then be wrong, and these warm-started solves do not take the
+ * log-domain path; z holds the last good iterate. */
 int pd_barycenter(pdsink_ctx* ctx, int64_t n_diag, const float* hist,
                   double lambda, int32_t max_outer, double energy_rtol, int32_t init_uniform,
                   float* z, double* energy, int32_t* outer,
@@ -208,6 +215,21 @@ int kmeans_lloyd(pdsink_ctx* ctx, int64_t n_diag, const float* hist, int32_t k, 
                  int32_t rounds, double lambda, int32_t max_outer, double energy_rtol,
                  float* centroids, int32_t* assign, double* objective,
                  void* ws, size_t ws_bytes, void* stream);
+
+/* Phase cycle counters of the resident-kernel distance path, for performance
+ * work.  Only a library built with PDSINK_PROFILE=1 (python -m
+ * paper_1805_08331_amd.build --profile, libpdsink_prof.so) records them; the
+ * plain library returns PDSINK_EINVAL.  Copies PDSINK_NPHASE counters summed
+ * over every pair that path solved on the current device since the last
+ * reset into out (host), in the order: cycles of setup, scale normalisers,
+ * BF16 kernel builds, contraction 1, contraction 2, first update pass,
+ * suspects, refits, final update pass, cost; then the numbers of half steps,
+ * refits, kernel builds, normaliser computations, half steps with suspects
+ * and pairs.  Cycles are those of the shader clock counter between workgroup
+ * barriers, as seen by the first wave.  reset != 0 clears the counters.
+ * Synchronises the device. */
+#define PDSINK_NPHASE 16
+int pdsink_phase_profile(uint64_t* out, int reset);
 
 /* Static string for a PDSINK_* return code. */
 const char* pdsink_strerror(int code);

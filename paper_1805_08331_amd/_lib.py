@@ -9,7 +9,10 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpdsink.so")
+# PDSINK_PROFILE_BUILD=1 selects the instrumented build (phase cycle counters,
+# python -m paper_1805_08331_amd.build --profile); it computes the same results.
+LIB_NAME = "libpdsink_prof.so" if os.environ.get("PDSINK_PROFILE_BUILD") == "1" else "libpdsink.so"
+LIB_PATH = os.path.join(HERE, LIB_NAME)
 
 c_int = ctypes.c_int
 c_i32 = ctypes.c_int32
@@ -58,6 +61,7 @@ SIGNATURES = {
     "pdsink_ctx_params": (c_int, [c_vp, ctypes.POINTER(Params)]),
     "pdsink_workspace_bytes": (c_int, [c_vp, c_int, c_i64, ctypes.POINTER(c_size)]),
     "pd_discretize": (c_int, [c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp]),
+    "pdsink_phase_profile": (c_int, [c_vp, c_int]),
     "sinkhorn_dist_batch": (c_int, [c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
                                     c_vp, c_size, c_vp]),
     "sinkhorn_dist_bounds_batch": (c_int, [c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,

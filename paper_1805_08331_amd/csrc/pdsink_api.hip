@@ -13,6 +13,7 @@
 #include "pdsink_device.h"
 #include "sinkhorn_log.h"
 #include "sinkhorn_pair.h"
+#include "sinkhorn_fast.h"
 
 using namespace pdsink;
 
@@ -223,6 +224,24 @@ template <int D>
 int launch_levels(PairParams pp, int n_slots, hipStream_t st) {
   if (pp.upper || pp.lower) return launch_pair_bounds(D, pp, n_slots, st) ? PDSINK_EDEVICE : PDSINK_OK;
   pp.only_redo = 0;
+  if constexpr (D == 128) {
+    // Grids up to 100 without warm start or gradient output: the resident-kernel
+    // variant; pairs it does not take (supports beyond 512 cells or below the
+    // diagonal, suspect-list overflow) go to the global-list launch.
+    if (pp.d <= FAST_DMAX && !pp.state && !pp.gout) {
+      const unsigned g = (unsigned)pp.n_pairs;
+      switch ((pp.d + 15) / 16) {
+        case 5: hipLaunchKernelGGL(sinkhorn_fast_kernel<5>, dim3(g), dim3(PWGS), 0, st, pp); break;
+        case 6: hipLaunchKernelGGL(sinkhorn_fast_kernel<6>, dim3(g), dim3(PWGS), 0, st, pp); break;
+        default: hipLaunchKernelGGL(sinkhorn_fast_kernel<7>, dim3(g), dim3(PWGS), 0, st, pp); break;
+      }
+      int rc = last_error();
+      if (rc) return rc;
+      pp.only_redo = 1;
+      hipLaunchKernelGGL((sinkhorn_pair_kernel<D, 0>), dim3((unsigned)n_slots), dim3(PWGS), 0, st, pp);
+      return last_error();
+    }
+  }
   // beyond D = 128 every launch strides over the batch with one operand slice per slot
   const unsigned g0 = D > 128 ? (unsigned)n_slots : (unsigned)pp.n_pairs;
   hipLaunchKernelGGL((sinkhorn_pair_kernel<D, 1>), dim3(g0), dim3(PWGS), 0, st, pp);
@@ -668,7 +687,10 @@ int pd_barycenter(pdsink_ctx* ctx, int64_t n_diag, const float* hist, double lam
       return PDSINK_EDEVICE;
     double sum = 0.0;
     for (int64_t q = 0; q < N; ++q) {
-      if (hs[q] & PDSINK_ST_NONFINITE) return PDSINK_ERANGE;
+      // A solve whose scaled iterates left the representable range (the log
+      // domain path does not serve the barycenter's warm-started solves) would
+      // feed a wrong cost and gradient into the step: refuse it.
+      if (hs[q] & (PDSINK_ST_NONFINITE | PDSINK_ST_RANGE)) return PDSINK_ERANGE;
       sum += hc[q];
     }
     E = sum / (double)N;
@@ -683,6 +705,27 @@ int pd_barycenter(pdsink_ctx* ctx, int64_t n_diag, const float* hist, double lam
   *energy = E;
   *outer = t + 1;
   return PDSINK_OK;
+}
+
+int pdsink_phase_profile(uint64_t* out, int reset) {
+#if PDSINK_PROFILE
+  if (!out) return PDSINK_EINVAL;
+  unsigned long long h[PH_COUNT];
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpyFromSymbol(h, HIP_SYMBOL(g_phase), sizeof(h), 0, hipMemcpyDeviceToHost) != hipSuccess)
+    return PDSINK_EDEVICE;
+  for (int k = 0; k < PH_COUNT; ++k) out[k] = h[k];
+  if (reset) {
+    const unsigned long long z[PH_COUNT] = {};
+    if (hipMemcpyToSymbol(HIP_SYMBOL(g_phase), z, sizeof(z), 0, hipMemcpyHostToDevice) != hipSuccess)
+      return PDSINK_EDEVICE;
+  }
+  return PDSINK_OK;
+#else
+  (void)out;
+  (void)reset;
+  return PDSINK_EINVAL;
+#endif
 }
 
 int pdsink_lloyd_workspace_bytes(const pdsink_ctx* ctx, int64_t n_diag, int32_t k, size_t* bytes) {

@@ -21,7 +21,7 @@ def _csv(path, counter, rows):
 
 def test_traffic_record_scales_by_the_copy(tmp_path):
     n = bench.NPAIRS
-    kern = "void pdsink::sinkhorn_pair_kernel<128, 1, false>(pdsink::PairParams)"
+    kern = f"void pdsink::{bench.PAIR_KERNEL_NAME}<7>(pdsink::PairParams)"
     fetch = [("__amd_rocclr_copyBuffer", 512, 3.0), (kern, n * 512, 1000.0),
              ("__amd_rocclr_copyBuffer", 131072, 131072.0)]   # the copy reads half its bytes per the counter
     write = [("__amd_rocclr_copyBuffer", 512, 1.0), (kern, n * 512, 10.0),

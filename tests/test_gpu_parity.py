@@ -5,7 +5,10 @@ iteration count the GPU reports, from the same start, and the Sinkhorn costs
 agree to 1e-5 relative.  BF16 contractions with FP32 refinement are compared
 with the converged oracle (the fixed point is unique) to 1e-3 relative.
 """
+import json
 import math
+import os
+import sys
 
 import numpy as np
 import pytest
@@ -18,6 +21,16 @@ pytestmark = pytest.mark.gpu
 
 FP32_RTOL = 1e-5
 BF16_RTOL = 1e-3
+
+GOLDEN_DIR = os.path.join(os.path.dirname(__file__), "golden")
+sys.path.insert(0, GOLDEN_DIR)
+import make_sinkhorn_golden as _golden  # noqa: E402  (rebuilds a case's histograms from its generator)
+
+
+def golden_cases():
+    """FP64 oracle results written by tests/golden/make_sinkhorn_golden.py (calls oracle/ only)."""
+    with open(os.path.join(GOLDEN_DIR, "sinkhorn_golden.json")) as fh:
+        return json.load(fh)["cases"]
 
 _C = {}
 
@@ -117,7 +130,10 @@ def test_benchmark_batch_sampled(pds):
         cost, iters, err, st, hist = run_pairs(pds, ctx, D1s, D2s)
     assert np.all(st == 0) and np.all(err <= 1e-3)
     assert np.all(iters[:, 0] == 0)
-    assert iters[:3, 1].tolist() == [157, 495, 348]      # FP64 oracle counts for pairs 0, 1, 2
+    # the FP64 oracle's iteration counts at tol 1e-3 for pairs 0, 1, 2 (golden file)
+    stops = {c["index"]: c for c in golden_cases() if c["kind"] == "stop_1e-3"}
+    for q in (0, 1, 2):
+        assert iters[q, 1] == stops[q]["iters"], (q, iters[q], stops[q]["iters"])
     C = dense_C(d)
     for q in (0, 1, 777):
         r = sinkhorn.sinkhorn(hist[q], hist[1024 + q], g, max_iter=int(iters[q, 1]), C=C)
@@ -508,3 +524,82 @@ def test_grid_beyond_128_same_schedule(pds):
         r = sinkhorn.sinkhorn(hist[q], hist[2 + q], g, max_iter=25, C=C)
         assert rel(cost[q], r.cost) <= FP32_RTOL, (q, cost[q], r.cost)
     _C.pop(d, None)
+
+
+def _run_hist_pairs(pds, ctx, A, B):
+    """Pairs (A[q], B[q]) of float64 histograms, uploaded as float32."""
+    n = len(A)
+    H = torch.from_numpy(np.stack(list(A) + list(B)).astype(np.float32)).to(ctx.device)
+    ia = torch.arange(0, n, dtype=torch.int32, device=ctx.device)
+    r = pds.sinkhorn_dist_batch(ctx, H, H, ia, ia + n)
+    torch.cuda.synchronize()
+    return r.cost.cpu().numpy(), r.iters.cpu().numpy(), r.err.cpu().numpy(), r.status.cpu().numpy()
+
+
+@pytest.mark.parametrize("switch_tol", [1.5e-3, 0.8e-3])
+def test_bf16_refine_d100_against_converged(pds, switch_tol):
+    """The grid and contractions the benchmark times (d = 100 padded to 128,
+    BF16 MFMA then FP32 refinement, gamma = 1e-3): refined to 1e-5, each pair's
+    cost is within 1e-3 of the FP64 oracle's converged fixed point (err <= 1e-7;
+    the fixed point is unique).  Pairs 0, 3, 10, 17 of the benchmark batch
+    (register lists) and a dense upper-triangular histogram against a diagram
+    (global lists, suspect arrays in the workspace).  Both the bench's switch
+    point (0.8e-3) and a later one."""
+    cases = [c for c in golden_cases() if c["kind"] == "converged" and c["d"] == 100]
+    assert len(cases) == 5
+    hs = [_golden.inputs(c) for c in cases]
+    with pds.Context(100, 1e-3, tol=1e-5, max_iter=20000, precision="bf16", switch_tol=switch_tol) as ctx:
+        cost, iters, err, st = _run_hist_pairs(pds, ctx, [h[0] for h in hs], [h[1] for h in hs])
+    for q, c in enumerate(cases):
+        assert st[q] == 0 and err[q] <= 1e-5, (c["name"], st[q], err[q])
+        assert iters[q, 0] > 0 and iters[q, 1] > 0, (c["name"], iters[q])
+        assert c["err"] <= 1e-6
+        r = rel(cost[q], c["cost"])
+        print(f"{c['name']}: bf16 {iters[q, 0]} + fp32 {iters[q, 1]} iterations, rel {r:.2e}")
+        assert r <= BF16_RTOL, (c["name"], cost[q], c["cost"])
+
+
+def test_bf16_refine_full_batch_against_converged(pds):
+    """The benchmark's launch (1024 pairs, d = 100, BF16 then FP32, switch at
+    0.8e-3) refined to 1e-5: every pair converges, and the pairs with a
+    converged oracle value match it to 1e-3."""
+    d, g = 100, 1e-3
+    D1s, D2s = pdgen.pairs_batch(0, 1024)
+    with pds.Context(d, g, tol=1e-5, max_iter=20000, precision="bf16", switch_tol=0.8e-3) as ctx:
+        cost, iters, err, st, hist = run_pairs(pds, ctx, D1s, D2s)
+    assert np.all(st == 0) and np.all(err <= 1e-5)
+    assert np.all(iters[:, 0] > 0)
+    for c in golden_cases():
+        if c["kind"] == "converged" and c["gen"]["kind"] == "pairs_batch" and c["gen"]["seed"] == 0:
+            q = c["index"]
+            assert rel(cost[q], c["cost"]) <= BF16_RTOL, (q, cost[q], c["cost"])
+
+
+def test_bf16_refine_grid_beyond_128_against_converged(pds):
+    """d = 136 (padded to 256: the BF16 contractions on global operand slices,
+    the grid class of the barycenter and serving workloads at d = 200),
+    gamma = 2e-3, refined to 1e-5: costs within 1e-3 of the converged oracle."""
+    cases = [c for c in golden_cases() if c["kind"] == "converged" and c["d"] == 136]
+    assert len(cases) == 2
+    assert all(c["err"] <= 1e-5 for c in cases)   # the oracle ran further than the GPU's 1e-5
+    hs = [_golden.inputs(c) for c in cases]
+    for sw in (1.5e-3, 0.8e-3):
+        with pds.Context(136, 2e-3, tol=1e-5, max_iter=20000, precision="bf16", switch_tol=sw) as ctx:
+            cost, iters, err, st = _run_hist_pairs(pds, ctx, [h[0] for h in hs], [h[1] for h in hs])
+        for q, c in enumerate(cases):
+            assert st[q] == 0 and err[q] <= 1e-5 and iters[q, 0] > 0, (c["name"], st[q], iters[q])
+            assert rel(cost[q], c["cost"]) <= BF16_RTOL, (c["name"], sw, cost[q], c["cost"])
+
+
+def test_barycenter_range_is_an_error(pds):
+    """A kernel so sharp (gamma d^2 = 0.02) that the barycenter's warm-started
+    inner solves leave the scaled representation: pd_barycenter reports
+    PDSINK_ERANGE instead of stepping with a wrong cost and gradient."""
+    d, g = 32, 2e-5
+    diags = pdgen.bary_set(7, n_diag=3, lo=10, hi=40, template_size=30)
+    hists = [ground.discretize(x, d) for x in diags]
+    with pds.Context(d, g, tol=1e-4, max_iter=2000) as ctx:
+        H = torch.from_numpy(np.stack(hists).astype(np.float32)).cuda()
+        with pytest.raises(pds.PdsinkError) as e:
+            pds.pd_barycenter(ctx, H, lam=5.0, max_outer=3, energy_rtol=0.0)
+        assert e.value.code == pds._lib.PDSINK_ERANGE
