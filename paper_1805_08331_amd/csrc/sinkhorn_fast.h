@@ -20,8 +20,8 @@
 // up to the MFMA depth 16), then two slots that alternate between half steps:
 // the input residual X (d + 1 rows, the last one zero for padded tile rows)
 // is read by contraction 1, whose output T^T goes to the other slot; the
-// result W of contraction 2 is stored packed (upper triangle, row i holds
-// columns i .. d-1) over the dead X; the update writes the new residual into
+// result W of contraction 2 is stored packed (upper triangle, column j holds
+// rows 0 .. j) over the dead X; the update writes the new residual into
 // the slot that held T^T, which the next half step reads as its X.  A half
 // step without refit, rebuild or suspect needs four workgroup barriers.
 // The FP32 phase (refinement, the FP32 form and the cost) computes kernel
@@ -37,6 +37,11 @@ constexpr int FAST_KD = 112;                    // FAST_DMAX rounded up to 16
 constexpr int FAST_LDB = FAST_KD + 8;           // BF16 row stride at most (16-byte aligned rows)
 constexpr int FAST_MAXSUSP = 128;               // suspects handled per half step
 constexpr int FAST_SPAN = 44;                   // residual span (octaves) kept without a refit
+// Margin (octaves) between the bound on what the contractions drop and a
+// trusted value: the FP32 unit roundoff for FP32 contractions; in the BF16
+// phase 2^-10, already below the rounding of the BF16 operands (2^-8 relative
+// per entry), since the FP32 refinement decides the result.
+constexpr int FAST_MARGIN_BF16 = 10;
 
 struct FastLayout {
   // BF16 phase
@@ -45,16 +50,16 @@ struct FastLayout {
   static constexpr int K1V = 0, K2V = KBYTES, K1U = 2 * KBYTES, K2U = 3 * KBYTES;
   static constexpr int S0 = 4 * KBYTES, S1 = S0 + SLOT;
   static constexpr int BIG = S1 + SLOT;
-  // packed W: d (d + 1) / 2 FP32 values; the staging of a support list after it
-  static constexpr int WP = ((FAST_DMAX * (FAST_DMAX + 1) / 2) * 4 + 15) & ~15;
-  static constexpr int STAGE = PWGS * 8;
+  // packed W (columns padded to multiples of 4 rows, 4 (a+1)(2a+b) floats
+  // before column j = 4a + b) and a 16-byte dummy slot per lane after it
+  static constexpr int WP = (4 * (FAST_DMAX / 4 + 1) * (2 * (FAST_DMAX / 4) + FAST_DMAX % 4) + 4 * 64) * 4;
   // FP32 phase: X [d + 1][KD + 1], T [KD][129], W packed + staging
   static constexpr int LTF = 128 + 1;
   static constexpr int FA = 0;
   static constexpr int FB = ((FAST_DMAX + 1) * (FAST_KD + 1) * 4 + 15) & ~15;
   static constexpr int FC = FB + ((FAST_KD * LTF * 4 + 15) & ~15);
-  static_assert(WP + STAGE <= SLOT, "packed W and the staging in one slot");
-  static_assert(FC + WP + STAGE <= BIG, "FP32 layout within the BF16 one");
+  static_assert(WP <= SLOT, "packed W in one slot");
+  static_assert(FC + WP <= BIG, "FP32 layout within the BF16 one");
 };
 
 struct FastSmem {
@@ -70,10 +75,19 @@ struct FastSmem {
   alignas(16) int Su[128];
   alignas(16) int Rv[128];
   alignas(16) int Sv[128];
+  // refit extrema; between refits the same bytes hold the staging of x's
+  // support list for the exact path (pass A to the suspects) and the terms
+  // of <y, k_Delta> (final pass to the next half step's contraction 2)
   alignas(16) int fit[2][4][128];
   int sflag, nsusp;
   double red[PNW], reds[PNW], redf[PNW];
   int rede[PNW], redi[PNW], redm[PNW];
+  // per-wave partial results of an update pass: error sum, flags, span
+  struct alignas(16) Rec {
+    double eg;
+    int flags;
+    int span;
+  } rec[PNW], rec2[PNW];
   int susp_cell[FAST_MAXSUSP], susp_e[FAST_MAXSUSP];
   float susp_m[FAST_MAXSUSP];
 };
@@ -87,8 +101,12 @@ static_assert(sizeof(FastSmem) <= 160 * 1024, "one workgroup's LDS");
 // below 2^-126, and the fewer cells need the exact evaluation.
 __device__ __forceinline__ int fast_headroom(int span) { return max(0, min(HEAD, (113 - span) >> 1)); }
 
-// Offset of row i in the packed upper triangle of a d x d grid.
-__device__ __forceinline__ int woff(int i, int d) { return i * d - ((i * (i - 1)) >> 1); }
+// Index of cell (i, j), i <= j, in the packed upper triangle stored by
+// columns, each padded to a multiple of 4 rows (so that 4 consecutive rows
+// starting at a multiple of 4 form one aligned 16-byte group): column j =
+// 4a + b starts at sum_{j' < j} 4 ceil((j' + 1) / 4) = 4 (a + 1)(2a + b).
+__device__ __forceinline__ int wcol(int j) { return 4 * ((j >> 2) + 1) * (2 * (j >> 2) + (j & 3)); }
+__device__ __forceinline__ int widx(int i, int j) { return wcol(j) + i; }
 
 // Per-side state beyond the support list.
 struct FSide {
@@ -100,6 +118,18 @@ struct FSide {
   bool fitted;   // the side has scales
   bool rs;       // R, S of the side's scales are current
   bool kern;     // the BF16 kernels of the side's scales are current
+  int rs_gen;    // bumped whenever R, S of the side are recomputed
+  int sc_gen;    // bumped whenever the side's scales are refit
+};
+
+// Per-thread constants of the update of one support entry of y from x, fixed
+// between refits: tagged with the generations of x's normalisers and y's scales.
+struct FCache {
+  int shp;       // P_y(i) + Q_y(j) + R_x(i) + S_x(j): log2 of y's scale over K x's
+  int e0;        // ge_Delta(j - i) - R_x(i) - S_x(j): the diagonal-bin term's exponent
+  float gdm;     // its mantissa
+  int edot;      // P_y(i) + Q_y(j) + ge_Delta(j - i): exponent of y_ij k_Delta,ij
+  int rs_tag, sc_tag;
 };
 
 // Phase cycle counters (library built with PDSINK_PROFILE=1 only): cycles
@@ -282,20 +312,24 @@ __device__ __forceinline__ void f_c1_chain(const __bf16* xa0, const __bf16* xa1,
                                            floatx16& acc1) {
   constexpr int S0 = TRIM ? 2 * TK0 : 0;
   constexpr int S1 = TRIM ? (2 * TK1 < NST ? 2 * TK1 : NST) : 0;
-  bf16x8 a0[NST], a1[NST], b[NST];
+  constexpr int PF = 4;   // steps in flight: a rotating register buffer
+  bf16x8 a0[PF], a1[PF], b[PF];
+  auto load = [&](int st) {
+    b[st % PF] = *reinterpret_cast<const bf16x8*>(kb + 16 * st);
+    a0[st % PF] = *reinterpret_cast<const bf16x8*>(xa0 + 16 * st);
+    if (st >= S1) a1[st % PF] = *reinterpret_cast<const bf16x8*>(xa1 + 16 * st);
+  };
 #pragma unroll
-  for (int st = S0; st < NST; ++st) {
-    b[st] = *reinterpret_cast<const bf16x8*>(kb + 16 * st);
-    a0[st] = *reinterpret_cast<const bf16x8*>(xa0 + 16 * st);
-    if (st >= S1) a1[st] = *reinterpret_cast<const bf16x8*>(xa1 + 16 * st);
-  }
-  // keep every read ahead of the MFMAs (the scheduler would otherwise sink
-  // them next to their use to save registers, and each MFMA would wait on one)
+  for (int st = S0; st < NST && st < S0 + PF; ++st) load(st);
+  // the order below is kept: the MFMAs of a step, then the reads of the step
+  // PF later into the registers they just consumed
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int st = S0; st < NST; ++st) {
-    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[st], b[st], acc0, 0, 0, 0);
-    if (st >= S1) acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[st], b[st], acc1, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[st % PF], b[st % PF], acc0, 0, 0, 0);
+    if (st >= S1) acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[st % PF], b[st % PF], acc1, 0, 0, 0);
+    if (st + PF < NST) load(st + PF);
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -318,7 +352,9 @@ __device__ __forceinline__ void f_c1_bf16(const __bf16* X, const __bf16* K2, __b
     if (trim) f_c1_chain<NST, 1, 2, true>(xa0, xa1, kb, acc0, acc1);
     else f_c1_chain<NST, 1, 2, false>(xa0, xa1, kb, acc0, acc1);
   }
-  mfma_drain();
+  // No explicit drain after the BF16 chains: the compiler's wait states
+  // before the first reads of the accumulators (s_nop 7 / 11 after
+  // v_mfma_f32_32x32x16_bf16) cover them (the FP32 chains keep mfma_drain).
   // Unconditional stores: rows j >= d go to the slot's spare row d + 1, and
   // groups of columns k >= KD to the pad columns KD .. KD + 3 of the row;
   // neither is ever read.
@@ -334,24 +370,24 @@ __device__ __forceinline__ void f_c1_bf16(const __bf16* X, const __bf16* K2, __b
   }
 }
 
-// Store of one 32 x 32 accumulator tile (rows ti, column j of the lane) into
-// the packed upper triangle, cells i <= j < d.  Row i0 + c of the lane lies
-// at offset base + c (E - 1) - c (c - 1) / 2 from the lane's first row (E =
-// d - i0: the length of row i0), with c a compile-time constant per
-// accumulator register; cells outside the triangle go to a dummy slot of the
-// lane just past it, so every store is unconditional.
-__device__ __forceinline__ void f_store_w(float* Wp, const floatx16& acc, int ti, int j, int d) {
-  const int lane = threadIdx.x & 63, lk = lane >> 5;
-  const int i0 = ti * 32 + 4 * lk;
-  const int dummy = ((d * (d + 1)) >> 1) + lane;
-  const int jr = j < d ? j - i0 : -1;      // rows i0 + c with c <= jr are stored
-  const int base = woff(i0, d) + j - i0;
-  const unsigned em1 = (unsigned)(d - i0 - 1) & 0xFFFFFFu;   // only used where c <= jr, i.e. i0 < d
+// Store of one 32 x 32 accumulator tile (row block ti, column block tj; the
+// lane holds column j = 32 tj + (lane mod 32) and rows i0 + 8q + t, q, t in
+// 0..3, in registers 4q + t) into the packed upper triangle: each group of 4
+// rows is one aligned 16-byte store.  A group whose first row lies on or
+// above the diagonal is stored whole (rows past j land in the column's
+// padding); other groups, and columns j >= d, go to a dummy slot of the lane.
+__device__ __forceinline__ void f_store_w(float* Wp, const floatx16& acc, int ti, int tj, int d) {
+  const int lane = threadIdx.x & 63, lr = lane & 31, lk = lane >> 5;
+  const int i0 = ti * 32 + 4 * lk, j = tj * 32 + lr;
+  float4* grp = reinterpret_cast<float4*>(Wp + widx(i0, j));
+  float4* dummy = reinterpret_cast<float4*>(Wp + wcol(d)) + lane;
+  const bool inside = ti < tj && tj * 32 + 31 < d;   // every group of the tile is stored
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int c = 8 * (r >> 2) + (r & 3);
-    const int idx = base + (int)__umul24((unsigned)c, em1) - ((c * (c - 1)) >> 1);
-    Wp[c <= jr ? idx : dummy] = acc[r];
+  for (int q = 0; q < 4; ++q) {
+    const float4 v = {acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
+    float4* dst = grp + 2 * q;
+    if (!inside) dst = (j < d && i0 + 8 * q <= j) ? dst : dummy;
+    *dst = v;
   }
 }
 
@@ -382,24 +418,27 @@ __device__ __forceinline__ void f_c2_bf16(const __bf16* K1, const __bf16* Tt, fl
   const __bf16* ka = K1 + min(i, d - 1) * LDB + 8 * lk;
   const __bf16* t0 = Tt + min(ja, d - 1) * LDB + 8 * lk;
   floatx16 acc0 = {}, acc1 = {};
+  constexpr int PF = 4;   // steps in flight: a rotating register buffer (as in contraction 1)
   if (w < 4) {
     const __bf16* t1 = Tt + min(ja + 32, d - 1) * LDB + 8 * lk;
-    bf16x8 a[NST], b0[NST], b1[NST];
+    bf16x8 a[PF], b0[PF], b1[PF];
+    auto load = [&](int st) {
+      a[st % PF] = *reinterpret_cast<const bf16x8*>(ka + 16 * st);
+      b0[st % PF] = *reinterpret_cast<const bf16x8*>(t0 + 16 * st);
+      b1[st % PF] = *reinterpret_cast<const bf16x8*>(t1 + 16 * st);
+    };
 #pragma unroll
-    for (int st = 0; st < NST; ++st) {
-      a[st] = *reinterpret_cast<const bf16x8*>(ka + 16 * st);
-      b0[st] = *reinterpret_cast<const bf16x8*>(t0 + 16 * st);
-      b1[st] = *reinterpret_cast<const bf16x8*>(t1 + 16 * st);
-    }
+    for (int st = 0; st < NST && st < PF; ++st) load(st);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int st = 0; st < NST; ++st) {
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[st], b0[st], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[st], b1[st], acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[st % PF], b0[st % PF], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[st % PF], b1[st % PF], acc1, 0, 0, 0);
+      if (st + PF < NST) load(st + PF);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    mfma_drain();
-    f_store_w(Wp, acc0, ti, ja, d);
-    f_store_w(Wp, acc1, ti, ja + 32, d);
+    f_store_w(Wp, acc0, ti, tj, d);
+    f_store_w(Wp, acc1, ti, tj + 1, d);
   } else {
     // chain a: steps [0, H), chain b: steps [H, NST)
     constexpr int H = (NST + 1) / 2;
@@ -415,10 +454,9 @@ __device__ __forceinline__ void f_c2_bf16(const __bf16* K1, const __bf16* Tt, fl
       acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[st], b[st], acc0, 0, 0, 0);
       if (H + st < NST) acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[H + st], b[H + st], acc1, 0, 0, 0);
     }
-    mfma_drain();
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc0[r] += acc1[r];
-    f_store_w(Wp, acc0, ti, ja, d);
+    f_store_w(Wp, acc0, ti, tj, d);
   }
 }
 
@@ -497,8 +535,8 @@ __device__ __forceinline__ void f_c2_fp32(const FastSmem& s, const float* T, flo
       b1 = nb1;
     }
     mfma_drain();
-    f_store_w(Wp, acc0, ti, ja, d);
-    f_store_w(Wp, acc1, ti, ja + 32, d);
+    f_store_w(Wp, acc0, ti, tj, d);
+    f_store_w(Wp, acc1, ti, tj + 1, d);
   } else {
     const int H2 = KD / 2;
     float a0 = f_kentry<WEIGHTED>(s, ia, lk, P, Ra), b0 = T[lk * LTF + ja];
@@ -517,7 +555,7 @@ __device__ __forceinline__ void f_c2_fp32(const FastSmem& s, const float* T, flo
     mfma_drain();
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc0[r] += acc1[r];
-    f_store_w(Wp, acc0, ti, ja, d);
+    f_store_w(Wp, acc0, ti, tj, d);
   }
 }
 
@@ -667,16 +705,17 @@ __device__ __forceinline__ void f_zero_x(void* buf, bool bf16, int d, int KD) {
 // scales yet) the scales are refit by two sweeps of row/column centring, and
 // y's normalisers and kernels become stale.  Writes the residual to nx and
 // returns <y, k_Delta> (grid part) in dot.
-__device__ __forceinline__ void f_update(FastSmem& s, const FBufs& b, SupList<1>& ys, int wix, const SupList<1>& xsup,
+__device__ __forceinline__ void f_update(FastSmem& s, const FBufs& b, SupList<1>& ys, int wix, FCache& cc,
+                                         bool lp_contract, const SupList<1>& xsup,
                                          bool x_dense, int d, int KD, const FSide& xs, int H, const int* Px,
                                          const int* Qx, const int* R, const int* S, int* Py, int* Qy, FSide& ysd,
-                                         bool check, double& err_out, bool& stop_out, ESum& dot, int& bad, int& range,
+                                         bool check, double& err_out, bool& stop_out, int& bad, int& range,
                                          double errD, double m, double tol, double switch_tol, bool& lowp, int t,
                                          int max_iter, FProf& pf) {
   constexpr int D = 128;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const float mxf = (float)xs.mx;
-  const int thr = H + max(xs.mres, 20) + 14 - 126 + SUSP_MARGIN;
+  const int thr = H + max(xs.mres, 20) + 14 - 126 + (lp_contract ? FAST_MARGIN_BF16 : SUSP_MARGIN);
   int* xcell = reinterpret_cast<int*>(b.stage);
   float* xres = reinterpret_cast<float*>(b.stage + PWGS * 4);
   const bool fitted = ysd.fitted;
@@ -690,12 +729,22 @@ __device__ __forceinline__ void f_update(FastSmem& s, const FBufs& b, SupList<1>
   int lover = 0, lbad = 0, span = 0;
   float cand = 0.0f;
   double eg = 0.0;
+  if (cc.rs_tag != xs.rs_gen || cc.sc_tag != ysd.sc_gen) {
+    // x's normalisers or y's scales changed: refresh the entry's constants
+    if (c >= 0) {
+      const int i = c / D, j = c % D, dl = j - i + D - 1;
+      cc.shp = Py[i] + Qy[j] + R[i] + S[j];
+      cc.e0 = s.tgde[dl] - R[i] - S[j];
+      cc.gdm = s.tgdm[dl];
+      cc.edot = Py[i] + Qy[j] + s.tgde[dl];
+    }
+    cc.rs_tag = xs.rs_gen;
+    cc.sc_tag = ysd.sc_gen;
+  }
   if (c >= 0) {
-    const int i = c / D, j = c % D;
     const float w = b.w[wix];
-    const int dl = j - i + D - 1;
-    const int E = xs.ex + s.tgde[dl] - R[i] - S[j];
-    const float Dm = mxf * s.tgdm[dl];
+    const int E = xs.ex + cc.e0;
+    const float Dm = mxf * cc.gdm;
     const int lw = w > 0.0f ? ilog2f(w) : QNONE;
     const int ld = Dm > 0.0f ? E + ilog2f(Dm) : QNONE;
     const int le = max(lw, ld);
@@ -714,7 +763,7 @@ __device__ __forceinline__ void f_update(FastSmem& s, const FBufs& b, SupList<1>
       const int qk = ilog2f(tg) - le;
       ys.set_q(0, qk);
       ys.set_qe(0, qk);
-      const int shp = Py[i] + Qy[j] + R[i] + S[j];
+      const int shp = cc.shp;
       if (check) {
         const double r = (double)ys.res(0);
         const double row = ldxd(r * (double)w, shp) + ldxd(r * (double)Dm, E + shp);
@@ -733,14 +782,10 @@ __device__ __forceinline__ void f_update(FastSmem& s, const FBufs& b, SupList<1>
   }
   f_zero_x(b.nx, b.nx_bf16, d, KD);
   {
-    const double egw = wave_sum(eg);
+    const double egw = check ? wave_sum(eg) : 0.0;
     const unsigned long long bb = __ballot(lbad), bo = __ballot(lover);
     const int sw = wave_max(span);
-    if (lane == 0) {
-      s.red[wave] = egw;
-      s.redi[wave] = (bb ? 1 : 0) | (bo ? 2 : 0);
-      s.redm[wave] = sw;
-    }
+    if (lane == 0) s.rec[wave] = FastSmem::Rec{egw, (bb ? 1 : 0) | (bo ? 2 : 0), sw};
   }
   __syncthreads();
   pf.mark(PH_PASSA);
@@ -749,9 +794,10 @@ __device__ __forceinline__ void f_update(FastSmem& s, const FBufs& b, SupList<1>
   int flags = 0, spn = 0;
 #pragma unroll
   for (int w = 0; w < PNW; ++w) {
-    egs += s.red[w];
-    flags |= s.redi[w];
-    spn = max(spn, s.redm[w]);
+    const FastSmem::Rec r = s.rec[w];
+    egs += r.eg;
+    flags |= r.flags;
+    spn = max(spn, r.span);
   }
 
   // Suspects: exact values, their error terms, candidates and spans.
@@ -767,24 +813,22 @@ __device__ __forceinline__ void f_update(FastSmem& s, const FBufs& b, SupList<1>
       const float sm = s.susp_m[id];
       const int qx = ilog2f(tg) - (se + ilog2f(sm));
       ys.set_qe(0, qx);
-      const int shp = Py[i] + Qy[j] + R[i] + S[j];
+      const int shp = cc.shp;
       if (check) eg2 = fabs(ldxd((double)ys.res(0) * (double)sm, se + shp) - (double)tg);
       if (fitted) {
         cand = tg / ldx(sm, se + shp);
         sp2 = abs(qx - shp);
       }
     }
-    eg2 = wave_sum(eg2);
+    eg2 = check ? wave_sum(eg2) : 0.0;
     sp2 = wave_max(sp2);
-    if (lane == 0) {
-      s.reds[wave] = eg2;
-      s.redm[wave] = sp2;
-    }
+    if (lane == 0) s.rec2[wave] = FastSmem::Rec{eg2, 0, sp2};
     __syncthreads();
 #pragma unroll
     for (int w = 0; w < PNW; ++w) {
-      egs += s.reds[w];
-      spn = max(spn, s.redm[w]);
+      const FastSmem::Rec r = s.rec2[w];
+      egs += r.eg;
+      spn = max(spn, r.span);
     }
     flags |= s.sflag;
     pf.count(PH_N_SUSPECT);
@@ -875,6 +919,7 @@ __device__ __forceinline__ void f_update(FastSmem& s, const FBufs& b, SupList<1>
     ysd.fitted = true;
     ysd.rs = false;
     ysd.kern = false;
+    ++ysd.sc_gen;
     // room for the residual to drift before the next refit
     ysd.span = max(FAST_SPAN, mres);
     ysd.H = fast_headroom(ysd.span);
@@ -886,34 +931,53 @@ __device__ __forceinline__ void f_update(FastSmem& s, const FBufs& b, SupList<1>
   ysd.mres = mres;
   if (mres > 100) range |= 1;
 
-  // Final pass: the new residual, <y, k_Delta>.
-  ESum acc{NEG, 0.0};
+  // Final pass: the new residual, and y_ij k_Delta,ij as the thread's term of
+  // <y, k_Delta>, which the waves idle in the next half step's contraction 2
+  // sum (f_reduce_dot).  Each thread overwrites only its own staging entry.
+  int et = NEG;
+  float mt = 0.0f;
   if (c >= 0) {
-    const int i = c / D, j = c % D, dl = j - i + D - 1;
     ys.set_res(0, cand);
     f_put_x(b.nx, c, cand, b.nx_bf16, KD);
-    acc = ESum{Py[i] + Qy[j] + s.tgde[dl], (double)cand * (double)s.tgdm[dl]};
-  }
-  {
-    // arrays of their own: without a refit no barrier separates this pass
-    // from the reads of red/reds/redm above
-    const ESum aw = wave_esum(acc);
-    if (lane == 0) {
-      s.rede[wave] = aw.e;
-      s.redf[wave] = aw.s;
+    if (cc.sc_tag == ysd.sc_gen) {   // no refit in this update: the cached constants hold
+      et = cc.edot;
+      mt = cand * cc.gdm;
+    } else {
+      const int i = c / D, j = c % D, dl = j - i + D - 1;
+      et = Py[i] + Qy[j] + s.tgde[dl];
+      mt = cand * s.tgdm[dl];
     }
   }
+  s.fit[0][0][tid] = et;
+  reinterpret_cast<float*>(&s.fit[0][0][0])[PWGS + tid] = mt;
   __syncthreads();
-  // largest exponent first, then one scaled sum (a wave with no term has a
-  // zero mantissa and an exponent far below any other)
-  int emax = s.rede[0];
-#pragma unroll
-  for (int w = 1; w < PNW; ++w) emax = max(emax, s.rede[w]);
-  double tsum = 0.0;
-#pragma unroll
-  for (int w = 0; w < PNW; ++w) tsum += ldxd(s.redf[w], s.rede[w] - emax);
-  dot = ESum{emax, tsum};
   pf.mark(PH_FINAL);
+}
+
+// <y, k_Delta> from the terms the last update left in s.fit: waves 6 and 7
+// (idle in contraction 2) sum four terms per thread with explicit exponents,
+// then one record per wave; every thread combines the two records after the
+// next workgroup barrier (f_dot_result).
+__device__ __forceinline__ void f_reduce_dot(FastSmem& s) {
+  const int tid = threadIdx.x, w = tid >> 6;
+  if (w < PNW - 2) return;
+  const int* te = &s.fit[0][0][0];
+  const float* tm = reinterpret_cast<const float*>(te) + PWGS;
+  const int t0 = tid - (PNW - 2) * 64;
+  ESum a{NEG, 0.0};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float mk = tm[t0 + 128 * k];
+    if (mk > 0.0f) a = esum_add(a, ESum{te[t0 + 128 * k], (double)mk});
+  }
+  a = wave_esum(a);
+  if ((tid & 63) == 0) {
+    s.rede[w] = a.e;
+    s.redf[w] = a.s;
+  }
+}
+__device__ __forceinline__ ESum f_dot_result(const FastSmem& s) {
+  return esum_add(ESum{s.rede[PNW - 2], s.redf[PNW - 2]}, ESum{s.rede[PNW - 1], s.redf[PNW - 1]});
 }
 
 // Operand pointers of the BF16 layout.
@@ -956,8 +1020,8 @@ __device__ __forceinline__ void fast_solve_pair(const PairParams& prm, FastSmem&
   int wix_a = 0, wix_b = 0;
   {
     const int ca = ua.cell(0), cb = vb.cell(0);
-    if (ca >= 0) wix_a = woff(ca / D, d) + ca % D - ca / D;
-    if (cb >= 0) wix_b = woff(cb / D, d) + cb % D - cb / D;
+    if (ca >= 0) wix_a = widx(ca / D, ca % D);
+    if (cb >= 0) wix_b = widx(cb / D, cb % D);
   }
   const double aD = mB, bD = mA, m = mA + mB;
   if (m <= 0.0) {
@@ -973,10 +1037,11 @@ __device__ __forceinline__ void fast_solve_pair(const PairParams& prm, FastSmem&
 
   bool lowp = prm.precision == 1;
   ESum kv{NEG, 0.0};
-  FSide su{0, 0.0, 0, HEAD, FAST_SPAN, false, false, false};
+  FSide su{0, 0.0, 0, HEAD, FAST_SPAN, false, false, false, 0, 0};
   // v = 1: scales 0, residual 1; full headroom, and the span that headroom
   // allows before v's first refit
-  FSide sv{0, 1.0, 0, HEAD, 113 - 2 * HEAD, true, false, false};
+  FSide sv{0, 1.0, 0, HEAD, 113 - 2 * HEAD, true, false, false, 0, 0};
+  FCache cache_u{0, 0, 0.0f, 0, -1, -1}, cache_v{0, 0, 0.0f, 0, -1, -1};
   // v = 1 on every grid cell and on the diagonal bin, in the X format of the
   // first half step
   int p = 0;                                  // BF16 phase: X in slot p
@@ -1009,8 +1074,14 @@ __device__ __forceinline__ void fast_solve_pair(const PairParams& prm, FastSmem&
   __syncthreads();
   pf.mark(PH_SETUP);
 
-  // One half step: y = target / (K x).
-  auto half = [&](bool u_update, bool lp_now, bool check, double errD, bool& stop) -> ESum {
+  // The grid part of <y, k_Delta> of the last update waits, as per-thread
+  // terms, for the idle waves of the next half step's contraction 2.
+  bool pend = false;
+
+  // One half step: y = target / (K x).  After contraction 2 the diagonal-bin
+  // entry of K x is complete: (K v)_Delta before a u-update, (K u)_Delta
+  // before a v-update.
+  auto half = [&](bool u_update, bool lp_now, bool check, bool& stop) {
     FSide& xd = u_update ? sv : su;
     FSide& yd = u_update ? su : sv;
     SupList<1>& ys = u_update ? ua : vb;
@@ -1028,6 +1099,7 @@ __device__ __forceinline__ void fast_solve_pair(const PairParams& prm, FastSmem&
       f_compute_RS(s, Px, Qx, d, H, Rx, Sx);
       xd.rs = true;
       xd.kern = false;
+      ++xd.rs_gen;
       __syncthreads();
       pf.count(PH_N_SCALES);
       pf.mark(PH_SCALES);
@@ -1054,9 +1126,10 @@ __device__ __forceinline__ void fast_solve_pair(const PairParams& prm, FastSmem&
       f_c1_bf16<NST>(reinterpret_cast<const __bf16*>(sx), K2, reinterpret_cast<__bf16*>(so), d, LDB, !xdense);
       __syncthreads();
       pf.mark(PH_C1);
+      if (pend) f_reduce_dot(s);
       f_c2_bf16<NST>(K1, reinterpret_cast<const __bf16*>(so), reinterpret_cast<float*>(sx), d, LDB);
       bf.w = reinterpret_cast<float*>(sx);   // over the dead X
-      bf.stage = sx + L::WP;
+      bf.stage = reinterpret_cast<char*>(&s.fit[0][0][0]);
       bf.nx = so;                             // over the dead T^T
       bf.nx_bf16 = true;
     } else {
@@ -1066,9 +1139,10 @@ __device__ __forceinline__ void fast_solve_pair(const PairParams& prm, FastSmem&
       f_c1_fp32<false>(s, Xf, Tf, Qx, Sx, d, KD, !xdense);
       __syncthreads();
       pf.mark(PH_C1);
+      if (pend) f_reduce_dot(s);
       f_c2_fp32<false>(s, Tf, Wf, Px, Rx, d, KD);
       bf.w = Wf;
-      bf.stage = s.big + L::FC + L::WP;
+      bf.stage = reinterpret_cast<char*>(&s.fit[0][0][0]);
       bf.nx = Xf;
       bf.nx_bf16 = false;
     }
@@ -1078,47 +1152,52 @@ __device__ __forceinline__ void fast_solve_pair(const PairParams& prm, FastSmem&
     }
     __syncthreads();
     pf.mark(PH_C2);
-    ESum dot{NEG, 0.0};
+    if (pend) {
+      const ESum dp = f_dot_result(s);
+      if (u_update) kv = esum_add(dp, ESum{sv.ex, sv.mx});
+      else ku = esum_add(dp, ESum{su.ex, su.mx});
+      pend = false;
+    }
+    const double errD = (u_update && check) ? fabs(ldxd(su.mx * kv.s, su.ex + kv.e) - aD) : 0.0;
     double e = 0.0;
     const bool lp_before = lowp;
     // The switch to FP32 is decided by the error check inside a u-update; the
     // update then still writes the new residual in BF16, and it is rewritten
     // here in the FP32 layout (whose X lies over the v-side kernels, unused
     // from now on; the slots holding this update's K x are not touched).
-    f_update(s, bf, ys, u_update ? wix_a : wix_b, xl, xdense, d, KD, xd, H, Px, Qx, Rx, Sx, Py, Qy, yd, check, e,
-             stop, dot, bad, range,
+    f_update(s, bf, ys, u_update ? wix_a : wix_b, u_update ? cache_u : cache_v, lp_now, xl, xdense, d, KD, xd, H,
+             Px, Qx, Rx, Sx, Py, Qy, yd, check, e, stop, bad, range,
              errD, m, prm.tol, prm.switch_tol, lowp, t, prm.max_iter, pf);
     if (check) err = e;
+    pend = !stop;
     if (!stop && lp_before && !lowp) {
       float* Xf = reinterpret_cast<float*>(s.big + L::FA);
       f_zero_x(Xf, false, d, KD);
       __syncthreads();
       const int c = ys.cell(0);
       if (c >= 0) f_put_x(Xf, c, ys.res(0), false, KD);
+      __syncthreads();
     }
+    // (the update's last barrier orders its writes of the new X before the
+    // next contraction reads them)
     if (lp_now) p ^= 1;
-    __syncthreads();
-    return dot;
   };
 
   for (;;) {
     // u-update: u = a / K v, after checking the marginal error of (u, v).
     const bool lp_now = lowp;
     bool stop = false;
-    const double errD = (t >= 1) ? fabs(ldxd(su.mx * kv.s, su.ex + kv.e) - aD) : 0.0;
-    const ESum dotu = half(true, lp_now, t >= 1, errD, stop);
+    half(true, lp_now, t >= 1, stop);   // also completes kv = (K v)_Delta
     if (stop || bad) break;
     if (range & 2) break;
     su.ex = -kv.e;
     su.mx = aD / kv.s;
-    ku = esum_add(dotu, ESum{su.ex, su.mx});
-    // v-update: v = b / K^T u (K is symmetric)
+    // v-update: v = b / K^T u (K is symmetric); completes ku = (K u)_Delta
     bool nostop = false;
-    const ESum dotv = half(false, lowp, false, 0.0, nostop);
+    half(false, lowp, false, nostop);
     v_dense = false;
     sv.ex = -ku.e;
     sv.mx = bD / ku.s;
-    kv = esum_add(dotv, ESum{sv.ex, sv.mx});
     ++t;
     if (lp_now) ++it_lp;
     else ++it_hp;
@@ -1167,8 +1246,8 @@ __device__ __forceinline__ void fast_solve_pair(const PairParams& prm, FastSmem&
   }
   const int ns = bad ? 0 : min(s.nsusp, FAST_MAXSUSP);
   if (ns > 0) {
-    int* xcell = reinterpret_cast<int*>(s.big + L::FC + L::WP);
-    float* xres = reinterpret_cast<float*>(s.big + L::FC + L::WP + PWGS * 4);
+    int* xcell = &s.fit[0][0][0];
+    float* xres = reinterpret_cast<float*>(xcell + PWGS);
     if (!v_dense) {
       const int c = vb.cell(0);
       xcell[tid] = c;
