@@ -221,7 +221,7 @@ def source_hash() -> str:
 def measured_traffic():
     """HBM bytes per launch of the pair kernel from the committed counter summary,
     or None when the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "sinkhorn_pair_kernel_d100_1024pairs_traffic.json")
+    path = os.path.join(ROOT, "profiles", "sinkhorn_fast_kernel_d100_1024pairs_traffic.json")
     try:
         with open(path) as fh:
             rec = json.load(fh)
@@ -263,7 +263,7 @@ def write_traffic(fetch_csv: str, write_csv: str, out: str | None = None):
            # two d x d FP32 histograms per pair in; cost, 2 iteration counts, error, status, route byte out
            "algorithmic_bytes": NPAIRS * (2 * 100 * 100 * 4 + 8 + 8 + 4 + 4 + 1)}
     if out is None:
-        out = os.path.join(ROOT, "profiles", "sinkhorn_pair_kernel_d100_1024pairs_traffic.json")
+        out = os.path.join(ROOT, "profiles", "sinkhorn_fast_kernel_d100_1024pairs_traffic.json")
     with open(out, "w") as fh:
         json.dump(rec, fh, indent=1)
         fh.write("\n")
@@ -347,6 +347,50 @@ def serve_bench(seconds: float, rate: float = 2000.0, k: int = 10, slots: int = 
         "data": "synthetic"}), flush=True)
 
 
+def bary_bench(outer: int = 3, n_diag: int = 256, d: int = 200, gamma: float = 2e-3, tol: float = 1e-4,
+               switch_tol: float = 1e-3) -> dict:
+    """The barycenter workload: ``n_diag`` perturbations of one template
+    (100-400 points, jitter 0.02, 10 % fresh points), d = 200, gamma = 2e-3,
+    BF16 contractions with FP32 refinement, inner solves to marginal error
+    ``tol``, warm-started between steps.  After one untimed step, ``outer``
+    steps of Algorithm 2 from the uniform start are timed end to end (the outer
+    loop synchronises with the host once per step, for its stopping test)."""
+    import torch
+    import pdgen
+    import paper_1805_08331_amd as pds
+
+    diags = pdgen.bary_set(0, n_diag=n_diag)
+    pts, off = pdgen.to_csr(diags)
+    with pds.Context(d, gamma, tol=tol, max_iter=20000, precision="bf16", switch_tol=switch_tol) as ctx:
+        hist, _, _ = pds.pd_discretize(ctx, torch.from_numpy(pts).cuda(), torch.from_numpy(off).cuda())
+        ws = ctx.workspace(pds._lib.PDSINK_OP_BARYCENTER, n_diag)
+        pds.pd_barycenter(ctx, hist, lam=5.0, max_outer=1, energy_rtol=0.0, ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        z, energy, n_out = pds.pd_barycenter(ctx, hist, lam=5.0, max_outer=outer, energy_rtol=0.0, ws=ws)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    return {"ms_per_outer_step": wall / n_out * 1e3, "outer_steps": n_out, "energy": energy,
+            "config": {"workload": f"barycenter of {n_diag} diagrams (100-400 points, one template, jitter 0.02, "
+                                   f"10% fresh points), d={d} grid + diagonal bin, gamma={gamma}",
+                       "precision": "bf16 contractions, fp32 refinement", "inner_tol": tol, "switch_tol": switch_tol,
+                       "lambda": 5.0}}
+
+
+def serve_leg(seconds: float = 3.0, rate: float = 2000.0) -> dict:
+    """The serving loop (serve_bench) in a child process, which sets its own
+    number of hardware queues before HIP starts: its JSON line, parsed."""
+    import subprocess
+    cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--serve", str(seconds), "--serve-rate", str(rate)]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=seconds * 10 + 240)
+    if r.returncode != 0:
+        return {"error": f"exit {r.returncode}: {r.stderr.strip().splitlines()[-1:]}"}
+    line = [x for x in r.stdout.splitlines() if x.startswith("{")][-1]
+    rec = json.loads(line)
+    return {k: rec[k] for k in ("p50_ms", "p99_ms", "max_ms", "requests", "offered_req_per_s", "served_req_per_s",
+                                "pairs_per_s", "bad_status_pairs", "by_grid", "config")}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -371,6 +415,10 @@ def main():
     ap.add_argument("--serve-hw-queues", type=int, default=16,
                     help="hardware queues of the process (GPU_MAX_HW_QUEUES, set before HIP starts; --serve)")
     ap.add_argument("--serve-max-pairs", type=int, default=512, help="pairs per launch at most (--serve)")
+    ap.add_argument("--bary", type=int, metavar="STEPS", default=None,
+                    help="time STEPS outer steps of the barycenter workload, print its line, then exit")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the barycenter and serving legs of the default line")
     ap.add_argument("--phases", choices=["bf16", "fp32"], default=None,
                     help="phase cycle split of one batch through the instrumented library, then exit")
     args = ap.parse_args()
@@ -402,6 +450,9 @@ def main():
 
     if args.pmc_probe:
         pmc_probe(pts_d, off_d, args.switch_tol)
+        return
+    if args.bary is not None:
+        print(json.dumps(bary_bench(args.bary)), flush=True)
         return
     if args.phases:
         phase_profile(pts_d, off_d, args.switch_tol, args.phases)
@@ -497,6 +548,14 @@ def main():
         # BF16 refined to 1e-5 with the converged oracle)
         out["bf16_vs_fp32_cost_rel"] = {"max": float(rd.max()), "median": float(np.median(rd))}
     out["iterations_per_pair"] = m["iters_quantiles"]
+    if not args.no_extra:
+        print("barycenter leg", file=sys.stderr, flush=True)
+        try:
+            out["barycenter"] = bary_bench(3)
+        except Exception as e:   # reported in the line, the headline figures stand
+            out["barycenter"] = {"error": repr(e)}
+        print("serving leg", file=sys.stderr, flush=True)
+        out["serving"] = serve_leg()
     if not args.no_cpu:
         oc, out["cpu_baseline"] = cpu_baseline()
         n = len(oc)

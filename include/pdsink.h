@@ -86,8 +86,10 @@ int pdsink_ctx_params(const pdsink_ctx* ctx, pdsink_params* out);
 #define PDSINK_OP_DIST        0
 #define PDSINK_OP_KMEANS      1
 #define PDSINK_OP_BARYCENTER  2
-/* Workspace (device bytes) an operation needs for `n_items` (pairs for DIST,
- * diagrams x centroids for KMEANS, diagrams for BARYCENTER).  (host) bytes. */
+#define PDSINK_OP_DIST_WARM   3   /* sinkhorn_dist_batch with a warm-start state */
+/* Workspace (device bytes) an operation needs for `n_items` (pairs for DIST and
+ * DIST_WARM, diagrams x centroids for KMEANS, diagrams for BARYCENTER).
+ * (host) bytes. */
 int pdsink_workspace_bytes(const pdsink_ctx* ctx, int op, int64_t n_items, size_t* bytes);
 
 /* Discretisation (section 3, "Discretization"; supplementary, error control
@@ -108,18 +110,33 @@ int pd_discretize(pdsink_ctx* ctx, const float* pts, const int64_t* offsets, int
 /* Algorithm 1 for a batch of pairs.  Pair q transports
  * a = (hist_a[ia[q]], |hist_b[ib[q]]|) onto b = (hist_b[ib[q]], |hist_a[ia[q]]|)
  * (Proposition 1: D1 + R D2 onto D2 + R D1).  Iterates the Sinkhorn map
- * (section 2) in alternating form from v = 1, u-update first, applying K by
- * Proposition 2, until the marginal error dist(P, Pi(a,b)) / m <= tol or
- * max_iter iterations, then returns the Sinkhorn cost <P_t, C> of
- * Proposition 3, reduced in FP64.
+ * (section 2) in alternating form from an initial v (Algorithm 1's initial
+ * (u, v): the first half step computes u from v, so only v is an input),
+ * u-update first, applying K by Proposition 2, until the marginal error
+ * dist(P, Pi(a,b)) / m <= tol or max_iter iterations, then returns the
+ * Sinkhorn cost <P_t, C> of Proposition 3, reduced in FP64.
  *   hist_a, hist_b (device) float32 [*, d, d]  histogram pools (may alias)
  *   ia, ib         (device) int32   [n_pairs]  indices into the pools
+ *   state          (device) double  [n_pairs, d*d + 1] in/out, may be NULL:
+ *                  natural log of v on the grid cells (row-major, as the
+ *                  histograms) and on the diagonal bin (last entry); -inf is
+ *                  v = 0.  NULL starts from v = 1 on every cell and the bin.
+ *                  Given, the solve starts from this v on supp(b) and the bin
+ *                  (entries off supp(b) are read as 0: the first v-update
+ *                  zeroes them anyway) and, on return, state holds log v_t
+ *                  (-inf off supp(b)).  A v whose log2 spans more than about
+ *                  200 octaves within the grid after row and column scaling
+ *                  sets PDSINK_ST_RANGE.  With a state the workspace is
+ *                  pdsink_workspace_bytes(DIST_WARM, n_pairs), the pairs run
+ *                  in the general kernels (not the resident d <= 100 variant),
+ *                  and pairs flagged NONFINITE or RANGE keep their flags (no
+ *                  log-domain re-solve: its iterates have no scaled v).
  *   cost           (device) double  [n_pairs]  out: <P_t, C>
  *   iters          (device) int32   [n_pairs, 2] out: iterations in BF16, in FP32
  *   err            (device) float   [n_pairs]  out: marginal error / m at stopping
  *   status         (device) int32   [n_pairs]  out: PDSINK_ST_* bits
  *   ws, ws_bytes   (device) workspace of at least pdsink_workspace_bytes(DIST, n_pairs)
- *                  bytes (one routing byte per pair); PDSINK_ENOMEM if smaller
+ *                  bytes (DIST_WARM with a state); PDSINK_ENOMEM if smaller
  * Masses are the histogram sums.  n_pairs = 0 is a no-op.  Any support size
  * is accepted: pairs whose supports exceed the register lists (512 cells per
  * side) run again with their lists in the workspace, from the same launch
@@ -133,7 +150,7 @@ int pd_discretize(pdsink_ctx* ctx, const float* pts, const int64_t* offsets, int
  * PDSINK_ST_LOG_PATH, iterations reported in the FP32 slot. */
 int sinkhorn_dist_batch(pdsink_ctx* ctx, int64_t n_pairs,
                         const float* hist_a, const float* hist_b,
-                        const int32_t* ia, const int32_t* ib,
+                        const int32_t* ia, const int32_t* ib, double* state,
                         double* cost, int32_t* iters, float* err, int32_t* status,
                         void* ws, size_t ws_bytes, void* stream);
 

@@ -135,17 +135,7 @@ class DistResult:
     lower: torch.Tensor | None = None   # float64 [n]: c-transform dual bound (bounds=True)
 
 
-def sinkhorn_dist_batch(ctx: Context, hist_a: torch.Tensor, hist_b: torch.Tensor, ia: torch.Tensor,
-                        ib: torch.Tensor, out: DistResult | None = None, ws: torch.Tensor | None = None,
-                        check_indices: bool = True, bounds: bool = False) -> DistResult:
-    """Algorithm 1 on pairs (hist_a[ia[q]], hist_b[ib[q]]).
-
-    ``bounds`` also returns the error-control bounds of section 3 in
-    ``upper`` and ``lower`` (lower <= exact transport value <= upper).
-
-    ``check_indices`` reads the index ranges back to the host (a stream
-    synchronisation); pass False inside graph capture, where the caller
-    guarantees that every index addresses its pool."""
+def _pair_args(ctx, hist_a, hist_b, ia, ib, out, check_indices):
     dev = ctx.device
     for t, nm in ((hist_a, "hist_a"), (hist_b, "hist_b")):
         _need(t, nm, torch.float32, dev)
@@ -164,8 +154,35 @@ def sinkhorn_dist_batch(ctx: Context, hist_a: torch.Tensor, hist_b: torch.Tensor
                          torch.empty((n, 2), dtype=torch.int32, device=dev),
                          torch.empty(n, dtype=torch.float32, device=dev),
                          torch.empty(n, dtype=torch.int32, device=dev))
+    return n, out
+
+
+def sinkhorn_dist_batch(ctx: Context, hist_a: torch.Tensor, hist_b: torch.Tensor, ia: torch.Tensor,
+                        ib: torch.Tensor, out: DistResult | None = None, ws: torch.Tensor | None = None,
+                        check_indices: bool = True, bounds: bool = False,
+                        state: torch.Tensor | None = None) -> DistResult:
+    """Algorithm 1 on pairs (hist_a[ia[q]], hist_b[ib[q]]).
+
+    ``bounds`` also returns the error-control bounds of section 3 in
+    ``upper`` and ``lower`` (lower <= exact transport value <= upper).
+
+    ``state`` (float64 [n, d*d + 1]: natural log of v on the grid cells, then
+    the diagonal bin) is Algorithm 1's initial v, overwritten with log v at
+    stopping; None starts from v = 1.  Not combined with ``bounds``.
+
+    ``check_indices`` reads the index ranges back to the host (a stream
+    synchronisation); pass False inside graph capture, where the caller
+    guarantees that every index addresses its pool."""
+    dev = ctx.device
+    n, out = _pair_args(ctx, hist_a, hist_b, ia, ib, out, check_indices)
+    if state is not None:
+        if bounds:
+            raise ValueError("state and bounds are not combined")
+        _need(state, "state", torch.float64, dev)
+        if state.shape != (n, ctx.d * ctx.d + 1):
+            raise ValueError(f"state must be [{n}, {ctx.d * ctx.d + 1}]")
     if ws is None:
-        ws = ctx.workspace(_lib.PDSINK_OP_DIST, n)
+        ws = ctx.workspace(_lib.PDSINK_OP_DIST if state is None else _lib.PDSINK_OP_DIST_WARM, n)
     if bounds:
         if out.upper is None:
             out.upper = torch.empty(n, dtype=torch.float64, device=dev)
@@ -176,7 +193,7 @@ def sinkhorn_dist_batch(ctx: Context, hist_a: torch.Tensor, hist_b: torch.Tensor
             _vp(out.err), _vp(out.status), _vp(out.upper), _vp(out.lower), _vp(ws), ws.numel(), _stream()))
         return out
     _lib.check("sinkhorn_dist_batch", _lib.load().sinkhorn_dist_batch(
-        ctx.handle, n, _vp(hist_a), _vp(hist_b), _vp(ia), _vp(ib), _vp(out.cost), _vp(out.iters),
+        ctx.handle, n, _vp(hist_a), _vp(hist_b), _vp(ia), _vp(ib), _vp(state), _vp(out.cost), _vp(out.iters),
         _vp(out.err), _vp(out.status), _vp(ws), ws.numel(), _stream()))
     return out
 

@@ -53,6 +53,7 @@ PDSINK_ST_LOG_PATH = 8
 PDSINK_OP_DIST = 0
 PDSINK_OP_KMEANS = 1
 PDSINK_OP_BARYCENTER = 2
+PDSINK_OP_DIST_WARM = 3
 
 # name -> (restype, argtypes); every function declared in include/pdsink.h
 SIGNATURES = {
@@ -62,7 +63,7 @@ SIGNATURES = {
     "pdsink_workspace_bytes": (c_int, [c_vp, c_int, c_i64, ctypes.POINTER(c_size)]),
     "pd_discretize": (c_int, [c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp]),
     "pdsink_phase_profile": (c_int, [c_vp, c_int]),
-    "sinkhorn_dist_batch": (c_int, [c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
+    "sinkhorn_dist_batch": (c_int, [c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
                                     c_vp, c_size, c_vp]),
     "sinkhorn_dist_bounds_batch": (c_int, [c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
                                            c_vp, c_vp, c_vp, c_size, c_vp]),

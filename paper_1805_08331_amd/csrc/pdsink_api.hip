@@ -417,6 +417,177 @@ __global__ void gather_hist_kernel(const float* __restrict__ hist, const int32_t
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < dd; c += gridDim.x * blockDim.x) out[m * dd + c] = src[c];
 }
 
+// Algorithm 1's initial v for sinkhorn_dist_batch: the natural log of v on the
+// d x d grid cells and on the diagonal bin, [n_pairs][d * d + 1], to the scaled
+// form the pair kernel starts from (WarmState).  Only the cells of supp(b)
+// (hist_b[ib[q]] > 0) are kept: v_ij = vres * 2^(Pv_i + Qv_j) with the row and
+// column log2 scales at the midranges of the integer parts of log2 v, so that
+// the residuals span at most +-mres octaves; every other cell gets vres = 0.
+// The diagonal bin: v_Delta = vmx 2^vex with vmx in [0.5, 1) (0 for -inf).
+template <int D>
+__global__ __launch_bounds__(WG) void warm_pack_kernel(const double* __restrict__ state,
+                                                       const float* __restrict__ hist_b,
+                                                       const int32_t* __restrict__ ib, int d,
+                                                       WarmState<D>* __restrict__ wsa) {
+  __shared__ int lo[D], hi[D], P[D], Q[D];
+  __shared__ int red[NWAVE];
+  const int tid = threadIdx.x;
+  const int64_t q = blockIdx.x;
+  const int dd = d * d;
+  const double* lv = state + q * (int64_t)(dd + 1);
+  const float* hb = hist_b + (int64_t)ib[q] * dd;
+  WarmState<D>& w = wsa[q];
+  constexpr double LOG2E = 1.4426950408889634074;
+  constexpr double LIM = (double)(1 << 22);   // |log2 v| beyond this: out of range anyway
+  auto expo = [&](int c, double& l2) -> bool {   // log2 v at a cell of supp(b), if finite
+    const double x = lv[c];
+    if (!(hb[c] > 0.0f) || !(x > -INFINITY) || !(x < INFINITY)) return false;
+    l2 = fmin(fmax(x * LOG2E, -LIM), LIM);
+    return true;
+  };
+  for (int i = tid; i < D; i += WG) {
+    lo[i] = INT_MAX;
+    hi[i] = INT_MIN;
+  }
+  __syncthreads();
+  for (int c = tid; c < dd; c += WG) {
+    double l2;
+    if (expo(c, l2)) {
+      const int e = (int)floor(l2);
+      atomicMin(&lo[c / d], e);
+      atomicMax(&hi[c / d], e);
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < D; i += WG) {
+    P[i] = hi[i] >= lo[i] ? (lo[i] + hi[i]) >> 1 : NEG;
+    lo[i] = INT_MAX;
+    hi[i] = INT_MIN;
+  }
+  __syncthreads();
+  for (int c = tid; c < dd; c += WG) {
+    double l2;
+    if (expo(c, l2)) {
+      const int e = (int)floor(l2) - P[c / d];
+      atomicMin(&lo[c % d], e);
+      atomicMax(&hi[c % d], e);
+    }
+  }
+  __syncthreads();
+  for (int j = tid; j < D; j += WG) Q[j] = hi[j] >= lo[j] ? (lo[j] + hi[j]) >> 1 : NEG;
+  __syncthreads();
+  int span = 0;
+  for (int c = tid; c < dd; c += WG) {
+    const int i = c / d, j = c % d;
+    double l2;
+    float r = 0.0f;
+    if (expo(c, l2)) {
+      const double t = l2 - (double)P[i] - (double)Q[j];
+      span = max(span, (int)fabs(floor(t)));
+      r = (float)exp2(t);
+    }
+    w.vres[i * D + j] = r;
+  }
+  span = wave_max(span);
+  if ((tid & 63) == 0) red[tid >> 6] = span;
+  for (int i = tid; i < D; i += WG) {
+    w.Pv[i] = P[i];
+    w.Qv[i] = Q[i];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int m = 0;
+    for (int k = 0; k < NWAVE; ++k) m = max(m, red[k]);
+    w.mres = m + 1;
+    const double x = lv[dd];
+    if (x > -INFINITY && x < INFINITY) {
+      const double l2 = fmin(fmax(x * LOG2E, -LIM), LIM);
+      const double e = floor(l2) + 1.0;
+      w.vex = (int)e;
+      w.vmx = exp2(l2 - e);
+    } else {
+      w.vex = 0;
+      w.vmx = 0.0;
+    }
+  }
+}
+
+// The final v of each pair (WarmState, written by the solve) back to the
+// natural log of v on the grid cells and the diagonal bin; -inf where v = 0
+// (every cell off supp(b)).
+template <int D>
+__global__ __launch_bounds__(WG) void warm_unpack_kernel(const WarmState<D>* __restrict__ wsa, int d,
+                                                         double* __restrict__ state) {
+  constexpr double LN2 = 0.69314718055994530942;
+  const int64_t q = blockIdx.x;
+  const int dd = d * d;
+  const WarmState<D>& w = wsa[q];
+  double* lv = state + q * (int64_t)(dd + 1);
+  for (int c = threadIdx.x; c < dd; c += WG) {
+    const int i = c / d, j = c % d;
+    const float r = w.vres[i * D + j];
+    lv[c] = (r > 0.0f && w.Pv[i] != NEG && w.Qv[j] != NEG)
+                ? (log2((double)r) + (double)w.Pv[i] + (double)w.Qv[j]) * LN2
+                : -INFINITY;
+  }
+  if (threadIdx.x == 0) lv[dd] = w.vmx > 0.0 ? (log2(w.vmx) + (double)w.vex) * LN2 : -INFINITY;
+}
+
+template <int D>
+int launch_warm(bool pack, const double* state_in, double* state_out, const float* hist_b, const int32_t* ib,
+                int d, int64_t n, char* ws, hipStream_t st) {
+  WarmState<D>* w = reinterpret_cast<WarmState<D>*>(ws);
+  if (pack)
+    hipLaunchKernelGGL(warm_pack_kernel<D>, dim3((unsigned)n), dim3(WG), 0, st, state_in, hist_b, ib, d, w);
+  else
+    hipLaunchKernelGGL(warm_unpack_kernel<D>, dim3((unsigned)n), dim3(WG), 0, st, w, d, state_out);
+  return last_error();
+}
+
+int warm_convert(int D, bool pack, double* state, const float* hist_b, const int32_t* ib, int d, int64_t n,
+                 char* ws, hipStream_t st) {
+  switch (D) {
+    case 32: return launch_warm<32>(pack, state, state, hist_b, ib, d, n, ws, st);
+    case 64: return launch_warm<64>(pack, state, state, hist_b, ib, d, n, ws, st);
+    case 128: return launch_warm<128>(pack, state, state, hist_b, ib, d, n, ws, st);
+    default: return launch_warm<256>(pack, state, state, hist_b, ib, d, n, ws, st);
+  }
+}
+
+// sinkhorn_dist_batch and sinkhorn_dist_bounds_batch: the workspace is the
+// routing flags, the list slots, the launch order and (with `state`) the
+// scaled warm-start records.
+int dist_impl(pdsink_ctx* ctx, int64_t n_pairs, const float* hist_a, const float* hist_b, const int32_t* ia,
+              const int32_t* ib, double* state, double* cost, int32_t* iters, float* err, int32_t* status,
+              double* upper, double* lower, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx || n_pairs < 0) return PDSINK_EINVAL;
+  if (n_pairs == 0) return PDSINK_OK;
+  if (n_pairs > INT_MAX || !hist_a || !hist_b || !ia || !ib || !cost || !iters || !err || !status)
+    return PDSINK_EINVAL;
+  size_t need = 0;
+  pdsink_workspace_bytes(ctx, state ? PDSINK_OP_DIST_WARM : PDSINK_OP_DIST, n_pairs, &need);
+  if (!ws || ws_bytes < need) return PDSINK_ENOMEM;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return PDSINK_EDEVICE;
+  const hipStream_t st = (hipStream_t)stream;
+  PairExtras ex;
+  ex.n_slots = (int)slots_for(ctx, n_pairs);
+  ex.lists = (char*)ws + align256(n_pairs);
+  ex.ops = ex.lists + ex.n_slots * list_bytes(ctx->D);
+  ex.order = ex.lists + ex.n_slots * slot_bytes(ctx->D);
+  ex.upper = upper;
+  ex.lower = lower;
+  if (state) {
+    ex.state = ex.order + order_bytes(n_pairs);
+    ex.state_in = 1;
+    const int rc = warm_convert(ctx->D, true, state, hist_b, ib, ctx->prm.d, n_pairs, ex.state, st);
+    if (rc) return rc;
+  }
+  int rc = run_pairs(ctx, n_pairs, hist_a, hist_b, ia, ib, cost, iters, err, status, (unsigned char*)ws, ex, st);
+  if (rc || !state) return rc;
+  return warm_convert(ctx->D, false, state, hist_b, ib, ctx->prm.d, n_pairs, ex.state, st);
+}
+
 extern "C" {
 
 const char* pdsink_strerror(int code) {
@@ -522,6 +693,10 @@ int pdsink_workspace_bytes(const pdsink_ctx* ctx, int op, int64_t n_items, size_
     case PDSINK_OP_DIST:   // routing flag per pair, support lists per slot, launch order
       *bytes = align256(n_items) + slots_for(ctx, n_items) * slot_bytes(ctx->D) + order_bytes(n_items);
       return PDSINK_OK;
+    case PDSINK_OP_DIST_WARM:   // the same, then one scaled warm-start record per pair
+      *bytes = align256(n_items) + slots_for(ctx, n_items) * slot_bytes(ctx->D) + order_bytes(n_items) +
+               align256(n_items * warm_bytes(ctx->D));
+      return PDSINK_OK;
     case PDSINK_OP_KMEANS:   // ia, ib, cost, iters, err, status, redo per pair, lists per slot, launch order
       *bytes = align256(n_items * 4) * 2 + align256(n_items * 8) + align256(n_items * 8) + align256(n_items * 4) * 2 +
                align256(n_items) + slots_for(ctx, n_items) * slot_bytes(ctx->D) + order_bytes(n_items);
@@ -553,34 +728,18 @@ int pd_discretize(pdsink_ctx* ctx, const float* pts, const int64_t* offsets, int
 }
 
 int sinkhorn_dist_batch(pdsink_ctx* ctx, int64_t n_pairs, const float* hist_a, const float* hist_b,
-                        const int32_t* ia, const int32_t* ib, double* cost, int32_t* iters, float* err,
-                        int32_t* status, void* ws, size_t ws_bytes, void* stream) {
-  return sinkhorn_dist_bounds_batch(ctx, n_pairs, hist_a, hist_b, ia, ib, cost, iters, err, status, nullptr,
-                                    nullptr, ws, ws_bytes, stream);
+                        const int32_t* ia, const int32_t* ib, double* state, double* cost, int32_t* iters,
+                        float* err, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+  return dist_impl(ctx, n_pairs, hist_a, hist_b, ia, ib, state, cost, iters, err, status, nullptr, nullptr, ws,
+                   ws_bytes, stream);
 }
 
 int sinkhorn_dist_bounds_batch(pdsink_ctx* ctx, int64_t n_pairs, const float* hist_a, const float* hist_b,
                                const int32_t* ia, const int32_t* ib, double* cost, int32_t* iters, float* err,
                                int32_t* status, double* upper, double* lower, void* ws, size_t ws_bytes,
                                void* stream) {
-  if (!ctx || n_pairs < 0) return PDSINK_EINVAL;
-  if (n_pairs == 0) return PDSINK_OK;
-  if (n_pairs > INT_MAX || !hist_a || !hist_b || !ia || !ib || !cost || !iters || !err || !status)
-    return PDSINK_EINVAL;
-  size_t need = 0;
-  pdsink_workspace_bytes(ctx, PDSINK_OP_DIST, n_pairs, &need);
-  if (!ws || ws_bytes < need) return PDSINK_ENOMEM;
-  DeviceGuard g(ctx->device);
-  if (!g.ok) return PDSINK_EDEVICE;
-  PairExtras ex;
-  ex.n_slots = (int)slots_for(ctx, n_pairs);
-  ex.lists = (char*)ws + align256(n_pairs);
-  ex.ops = ex.lists + ex.n_slots * list_bytes(ctx->D);
-  ex.order = ex.lists + ex.n_slots * slot_bytes(ctx->D);
-  ex.upper = upper;
-  ex.lower = lower;
-  return run_pairs(ctx, n_pairs, hist_a, hist_b, ia, ib, cost, iters, err, status, (unsigned char*)ws, ex,
-                   (hipStream_t)stream);
+  return dist_impl(ctx, n_pairs, hist_a, hist_b, ia, ib, nullptr, cost, iters, err, status, upper, lower, ws,
+                   ws_bytes, stream);
 }
 
 int kmeans_assign(pdsink_ctx* ctx, int64_t n_diag, const float* hist, int32_t k, const float* centroids,

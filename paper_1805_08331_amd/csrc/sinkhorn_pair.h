@@ -1921,6 +1921,7 @@ __device__ __forceinline__ void solve_pair(const PairParams& prm, PairSmem<D>& s
   ESum ku{NEG, 0.0};
 
   int t = 0, it_lp = 0, it_hp = 0, bad = 0, range = 0;
+  if (warm && sv.mres > 100) range |= 1;   // a warm start whose residuals FP32 cannot hold
   bool x_lp = lowp;      // format of the residual currently in the X buffer
   double err = INFINITY;
   __syncthreads();

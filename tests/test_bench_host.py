@@ -41,6 +41,6 @@ def test_committed_traffic_record_is_for_these_sources():
     """The committed counter record is reported only while the pair kernel's
     sources hash to the value it was taken on."""
     path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles",
-                        "sinkhorn_pair_kernel_d100_1024pairs_traffic.json")
+                        "sinkhorn_fast_kernel_d100_1024pairs_traffic.json")
     rec = json.load(open(path))
     assert bench.measured_traffic() == (rec["traffic_bytes"] if rec["source_hash"] == bench.source_hash() else None)

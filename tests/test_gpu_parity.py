@@ -121,6 +121,42 @@ def test_batch_same_schedule(pds, d, g, lo, hi):
         assert abs(ro.iters - t) <= 1
 
 
+@pytest.mark.parametrize("d,g,n,lo,hi", [(32, 5e-3, 4, 5, 80), (80, 2e-3, 2, 50, 300)])
+def test_warm_start_same_schedule(pds, d, g, n, lo, hi):
+    """Algorithm 1 from an initial v (the state argument): v from the oracle's
+    solve to marginal error 1e-2, then the GPU goes on to 1e-5 in FP32.  The
+    oracle warm-started from the same log v for the GPU's iteration count
+    gives the same cost (1e-5 relative) and the same log v_t on supp(b); the
+    state comes back with -inf off supp(b).  d = 80 runs the padded-128
+    general kernel, which the resident d <= 100 variant leaves to warm starts."""
+    D1s, D2s = pdgen.pairs_batch(d + 1, n, lo, hi)
+    C = dense_C(d)
+    with pds.Context(d, g, tol=1e-5, max_iter=20000) as ctx:
+        dev = ctx.device
+        pts, off = pdgen.to_csr(list(D1s) + list(D2s))
+        hist_t, _, _ = pds.pd_discretize(ctx, torch.from_numpy(pts).to(dev), torch.from_numpy(off).to(dev))
+        hist = hist_t.cpu().numpy().astype(np.float64)
+        coarse = [sinkhorn.sinkhorn(hist[q], hist[n + q], g, tol=1e-2, max_iter=20000, C=C) for q in range(n)]
+        state = torch.from_numpy(np.stack([r.log_v for r in coarse])).to(dev).contiguous()
+        ia = torch.arange(0, n, dtype=torch.int32, device=dev)
+        r = pds.sinkhorn_dist_batch(ctx, hist_t, hist_t, ia, ia + n, state=state)
+        torch.cuda.synchronize()
+        cost, iters, st = r.cost.cpu().numpy(), r.iters.cpu().numpy(), r.status.cpu().numpy()
+        lv = state.cpu().numpy()
+    for q in range(n):
+        t = int(iters[q].sum())
+        assert st[q] == 0 and 0 < t < 20000, (q, st[q], t)
+        o = sinkhorn.sinkhorn(hist[q], hist[n + q], g, max_iter=t, log_v0=coarse[q].log_v, C=C)
+        assert rel(cost[q], o.cost) <= FP32_RTOL, (q, cost[q], o.cost)
+        ow = sinkhorn.sinkhorn(hist[q], hist[n + q], g, tol=1e-5, max_iter=20000, log_v0=coarse[q].log_v, C=C)
+        assert abs(ow.iters - t) <= 1, (q, ow.iters, t)
+        sb = np.append(hist[n + q].ravel() > 0, hist[q].sum() > 0)
+        assert np.all(np.isneginf(lv[q][~sb]))
+        np.testing.assert_allclose(lv[q][sb], o.log_v[sb], rtol=0, atol=1e-4 * np.abs(o.log_v[sb]).max() + 1e-5)
+        # the warm start saves work: the cold solve to the same tolerance takes longer
+        assert ow.iters < sinkhorn.sinkhorn(hist[q], hist[n + q], g, tol=1e-5, max_iter=20000, C=C).iters
+
+
 def test_benchmark_batch_sampled(pds):
     """1024 pairs at d=100, gamma=1e-3, tol=1e-3 (the benchmark's launch); three
     pairs re-run by the oracle at the GPU's iteration counts."""
@@ -429,6 +465,26 @@ def test_barycenter_matches_oracle(pds, d, g, lo, hi):
     assert outer == ob.outer == 4
     assert rel(E, ob.energy) <= 1e-5, (E, ob.energy)
     np.testing.assert_allclose(z, ob.z, rtol=1e-4, atol=1e-6 * ob.z.max())
+
+
+def test_barycenter_bf16_grid_128_matches_oracle(pds):
+    """Algorithm 2 with BF16 contractions and FP32 refinement in the
+    warm-started inner solves, at d = 65 (padded grid 128, the global-list
+    variant for the dense barycenter support): three outer steps, energy to
+    1e-3 relative and z cell by cell against the FP64 oracle with inner solves
+    to the same tolerance."""
+    d, g = 65, 4e-3
+    diags = pdgen.bary_set(7, n_diag=4, lo=100, hi=300, template_size=200)
+    hists = [ground.discretize(x, d) for x in diags]
+    ob = barycenter.barycenter(hists, g, lam=5.0, tol=1e-5, max_inner=50000, max_outer=3, energy_rtol=0.0,
+                               C=dense_C(d))
+    with pds.Context(d, g, tol=1e-5, max_iter=50000, precision="bf16", switch_tol=1.5e-3) as ctx:
+        H = torch.from_numpy(np.stack(hists).astype(np.float32)).cuda()
+        z, E, outer = pds.pd_barycenter(ctx, H, lam=5.0, max_outer=3, energy_rtol=0.0)
+        z = z.cpu().numpy()
+    assert outer == ob.outer == 3
+    assert rel(E, ob.energy) <= 1e-3, (E, ob.energy)
+    np.testing.assert_allclose(z, ob.z, rtol=1e-3, atol=1e-4 * ob.z.max())
 
 
 def test_barycenter_energy_stop(pds):
