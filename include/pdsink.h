@@ -154,6 +154,32 @@ int sinkhorn_dist_batch(pdsink_ctx* ctx, int64_t n_pairs,
                         double* cost, int32_t* iters, float* err, int32_t* status,
                         void* ws, size_t ws_bytes, void* stream);
 
+/* sinkhorn_dist_batch with no workspace argument and no device allocation, for
+ * callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  The routing flags, launch order
+ * and support-list slots live in one static device array of
+ * PDSINK_NOALLOC_SCRATCH_BYTES, which every GPU the library runs on holds from
+ * the loading of the library's code until the process ends; its address is
+ * looked up when a context is created.  The caller passes inputs and outputs
+ * as for sinkhorn_dist_batch with state = NULL, and the results are the same
+ * bit for bit: the
+ * same kernels run, with as many list slots as the array holds (all of them at
+ * grids up to 128; 15 at grids beyond 128, where every launch strides over the
+ * batch, so there the call is slower).
+ * Errors: PDSINK_ENOMEM when n_pairs > PDSINK_NOALLOC_MAX_PAIRS; PDSINK_EDEVICE
+ * when the array's address could not be found on the context's device; others
+ * as sinkhorn_dist_batch.  Every call on one GPU uses that GPU's one array, and
+ * the array keeps the last call's contents (every byte a call reads is written
+ * by the same call first): calls that overlap on one GPU, from different
+ * streams or threads, race and must be serialised by the caller. */
+#define PDSINK_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+#define PDSINK_NOALLOC_MAX_PAIRS     ((int64_t)1 << 18)
+int sinkhorn_dist_batch_noalloc(pdsink_ctx* ctx, int64_t n_pairs,
+                                const float* hist_a, const float* hist_b,
+                                const int32_t* ia, const int32_t* ib,
+                                double* cost, int32_t* iters, float* err, int32_t* status,
+                                void* stream);
+
 /* sinkhorn_dist_batch plus the error control of section 3 ("Upper and Lower
  * Bounds"; Algorithm 1's optional outputs) for the final (u_t, v_t):
  *   upper (device) double [n_pairs] out, may be NULL: <R_t, C>, R_t the

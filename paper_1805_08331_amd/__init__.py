@@ -21,7 +21,8 @@ import torch
 from . import _lib
 from ._lib import PdsinkError  # noqa: F401
 
-__all__ = ["Context", "pd_discretize", "sinkhorn_dist_batch", "pd_barycenter", "kmeans_assign",
+__all__ = ["Context", "pd_discretize", "sinkhorn_dist_batch", "sinkhorn_dist_batch_noalloc", "pd_barycenter",
+           "kmeans_assign",
            "PdsinkError", "FP32", "BF16_REFINE"]
 
 FP32 = _lib.PDSINK_FP32
@@ -195,6 +196,19 @@ def sinkhorn_dist_batch(ctx: Context, hist_a: torch.Tensor, hist_b: torch.Tensor
     _lib.check("sinkhorn_dist_batch", _lib.load().sinkhorn_dist_batch(
         ctx.handle, n, _vp(hist_a), _vp(hist_b), _vp(ia), _vp(ib), _vp(state), _vp(out.cost), _vp(out.iters),
         _vp(out.err), _vp(out.status), _vp(ws), ws.numel(), _stream()))
+    return out
+
+
+def sinkhorn_dist_batch_noalloc(ctx: Context, hist_a: torch.Tensor, hist_b: torch.Tensor, ia: torch.Tensor,
+                                ib: torch.Tensor, out: DistResult | None = None,
+                                check_indices: bool = True) -> DistResult:
+    """``sinkhorn_dist_batch`` on the library's static scratch array: the call
+    allocates no device memory (pass ``out`` to allocate nothing here either).
+    At most ``PDSINK_NOALLOC_MAX_PAIRS`` pairs; calls that overlap on one GPU race."""
+    n, out = _pair_args(ctx, hist_a, hist_b, ia, ib, out, check_indices)
+    _lib.check("sinkhorn_dist_batch_noalloc", _lib.load().sinkhorn_dist_batch_noalloc(
+        ctx.handle, n, _vp(hist_a), _vp(hist_b), _vp(ia), _vp(ib), _vp(out.cost), _vp(out.iters),
+        _vp(out.err), _vp(out.status), _stream()))
     return out
 
 

@@ -50,6 +50,9 @@ PDSINK_ST_NONFINITE = 2
 PDSINK_ST_RANGE = 4
 PDSINK_ST_LOG_PATH = 8
 
+PDSINK_NOALLOC_SCRATCH_BYTES = 64 << 20
+PDSINK_NOALLOC_MAX_PAIRS = 1 << 18
+
 PDSINK_OP_DIST = 0
 PDSINK_OP_KMEANS = 1
 PDSINK_OP_BARYCENTER = 2
@@ -65,6 +68,7 @@ SIGNATURES = {
     "pdsink_phase_profile": (c_int, [c_vp, c_int]),
     "sinkhorn_dist_batch": (c_int, [c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
                                     c_vp, c_size, c_vp]),
+    "sinkhorn_dist_batch_noalloc": (c_int, [c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "sinkhorn_dist_bounds_batch": (c_int, [c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
                                            c_vp, c_vp, c_vp, c_size, c_vp]),
     "pd_barycenter": (c_int, [c_vp, c_i64, c_vp, c_dbl, c_i32, c_dbl, c_i32, c_vp,

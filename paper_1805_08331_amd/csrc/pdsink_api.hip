@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -16,6 +17,13 @@
 #include "sinkhorn_fast.h"
 
 using namespace pdsink;
+
+// Scratch of sinkhorn_dist_batch_noalloc: routing flags, launch order and the
+// per-slot support lists, in one array that each GPU holds from the loading of
+// this code object until the process ends.  In host code this name is not a
+// device address: host code uses the per-device address that
+// hipGetSymbolAddress returned (scratch_lookup), never the name itself.
+static __device__ __align__(256) unsigned char scratch[PDSINK_NOALLOC_SCRATCH_BYTES];
 
 namespace pdsink {
 // The bounds variant of the pair kernel (pdsink_bounds.hip).
@@ -36,9 +44,32 @@ struct pdsink_ctx {
   float* cd;
   int* kb;
   int n_cu;           // compute units of the device: workgroups of the global-list variant
+  void* scratch;      // device address of `scratch` on this device, NULL if the lookup failed
 };
 
 namespace {
+
+constexpr int MAX_DEVICES = 256;
+std::mutex scratch_mu;
+void* scratch_addr[MAX_DEVICES];
+
+// Device address of `scratch` on `device`, which must be the current device;
+// looked up once per device and kept.
+int scratch_lookup(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= MAX_DEVICES) return PDSINK_EINVAL;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_addr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();   // leave no sticky error for the next launch check
+      return PDSINK_EDEVICE;
+    }
+    scratch_addr[device] = p;
+  }
+  *out = scratch_addr[device];
+  return PDSINK_OK;
+}
 
 int pad_grid(int d) { return d <= 32 ? 32 : (d <= 64 ? 64 : (d <= 128 ? 128 : 256)); }
 
@@ -645,6 +676,9 @@ int pdsink_ctx_create(const pdsink_params* params, int device, pdsink_ctx** out)
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || ncu < 1) ncu = 1;
     ctx->n_cu = ncu;
   }
+  // With the context's device current: the no-allocation call's scratch.  A
+  // failed lookup leaves ctx->scratch NULL, and only that call reports it.
+  (void)scratch_lookup(device, &ctx->scratch);
   char* base = nullptr;
   const size_t bytes = (size_t)n * 4 * 7;
   if (hipMalloc(&base, bytes) != hipSuccess) {
@@ -732,6 +766,32 @@ int sinkhorn_dist_batch(pdsink_ctx* ctx, int64_t n_pairs, const float* hist_a, c
                         float* err, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
   return dist_impl(ctx, n_pairs, hist_a, hist_b, ia, ib, state, cost, iters, err, status, nullptr, nullptr, ws,
                    ws_bytes, stream);
+}
+
+int sinkhorn_dist_batch_noalloc(pdsink_ctx* ctx, int64_t n_pairs, const float* hist_a, const float* hist_b,
+                                const int32_t* ia, const int32_t* ib, double* cost, int32_t* iters, float* err,
+                                int32_t* status, void* stream) {
+  if (!ctx || n_pairs < 0) return PDSINK_EINVAL;
+  if (n_pairs == 0) return PDSINK_OK;
+  if (!hist_a || !hist_b || !ia || !ib || !cost || !iters || !err || !status) return PDSINK_EINVAL;
+  if (n_pairs > PDSINK_NOALLOC_MAX_PAIRS) return PDSINK_ENOMEM;
+  if (!ctx->scratch) return PDSINK_EDEVICE;
+  // The workspace of sinkhorn_dist_batch, carved from the scratch array: flags
+  // and launch order first, then as many list slots as the rest holds.
+  const size_t head = align256((size_t)n_pairs) + order_bytes(n_pairs);
+  const int64_t fit = (int64_t)((PDSINK_NOALLOC_SCRATCH_BYTES - head) / slot_bytes(ctx->D));
+  if (fit < 1) return PDSINK_ENOMEM;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return PDSINK_EDEVICE;
+  char* base = static_cast<char*>(ctx->scratch);
+  PairExtras ex;
+  const int64_t want = slots_for(ctx, n_pairs);
+  ex.n_slots = (int)(want < fit ? want : fit);
+  ex.order = base + align256((size_t)n_pairs);
+  ex.lists = ex.order + order_bytes(n_pairs);
+  ex.ops = ex.lists + ex.n_slots * list_bytes(ctx->D);
+  return run_pairs(ctx, n_pairs, hist_a, hist_b, ia, ib, cost, iters, err, status, (unsigned char*)base, ex,
+                   (hipStream_t)stream);
 }
 
 int sinkhorn_dist_bounds_batch(pdsink_ctx* ctx, int64_t n_pairs, const float* hist_a, const float* hist_b,
