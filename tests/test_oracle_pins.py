@@ -499,3 +499,59 @@ def test_lloyd_singleton_clusters():
         m = 2 * h.sum()
         assert 0.0 <= self_d[-1] <= 2 * g * m * math.log(m)
     assert math.isclose(hist[0], sum(self_d), rel_tol=1e-12)
+
+
+# --- Entropic sharpening (section 4, after Algorithm 2; readings in oracle/sharpen.py) ---
+
+def test_sharpen_hits_the_target_entropy_and_keeps_mass_and_order():
+    """The sharpened histogram has the target entropy (checked with scipy's own
+    entropy routine), the same mass and support, the same order of its cells,
+    and is a power of the input: log z' = beta log z + const on the support."""
+    from scipy.stats import entropy as sp_entropy
+    from oracle import sharpen
+    rng = np.random.default_rng(4)
+    z = np.triu(rng.gamma(0.7, 1.0, (12, 12)))
+    z[z < 0.2] = 0.0
+    h = sp_entropy(z[z > 0])
+    for h0 in (h - 0.3, h - 1.0, 1.5):
+        zs, beta = sharpen.sharpen(z, h0)
+        pos = z > 0
+        assert beta > 1.0
+        assert abs(sp_entropy(zs[pos]) - h0) < 1e-10
+        assert np.array_equal(zs > 0, pos)
+        assert abs(zs.sum() - z.sum()) < 1e-12 * z.sum()
+        order = np.argsort(z[pos], kind="stable")
+        assert np.all(np.diff(zs[pos][order]) >= -1e-15)
+        slope, icpt = np.polyfit(np.log(z[pos]), np.log(zs[pos]), 1)
+        assert abs(slope - beta) < 1e-8 * beta
+        assert np.allclose(np.log(zs[pos]), slope * np.log(z[pos]) + icpt, atol=1e-9)
+
+
+def test_sharpen_two_cells_closed_form():
+    """Two cells of masses x and 1 - x: the binary entropy of the sharpened
+    split equals h0, and its split is x^b / (x^b + (1-x)^b)."""
+    from oracle import sharpen
+    x = 0.3
+    z = np.array([[x, 1.0 - x]])
+    h0 = 0.4
+    zs, beta = sharpen.sharpen(z, h0)
+    q = zs[0, 0]
+    assert abs(-(q * math.log(q) + (1 - q) * math.log(1 - q)) - h0) < 1e-12
+    assert abs(q - x ** beta / (x ** beta + (1 - x) ** beta)) < 1e-12
+
+
+def test_sharpen_no_op_and_limits():
+    """At or below the target nothing changes (beta = 1); a target at or below
+    log n_max gives the even split over the maximal cells; a uniform histogram
+    cannot be sharpened and is its own limit."""
+    from oracle import sharpen
+    z = np.array([[4.0, 1.0, 1.0], [0.0, 2.0, 4.0], [0.0, 0.0, 0.5]])
+    zs, beta = sharpen.sharpen(z, sharpen.entropy(z) + 1e-9)
+    assert beta == 1.0 and np.array_equal(zs, z)
+    zs, beta = sharpen.sharpen(z, math.log(2.0))
+    assert beta == math.inf
+    np.testing.assert_allclose(zs, np.where(z == 4.0, z.sum() / 2, 0.0))
+    u = np.ones((3, 3))
+    zs, beta = sharpen.sharpen(u, 1.0)
+    np.testing.assert_allclose(zs, u)
+    assert sharpen.sharpen(np.zeros((2, 2)), 0.5)[1] == 1.0
