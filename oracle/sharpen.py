@@ -22,6 +22,7 @@ import math
 
 import numpy as np
 from scipy.optimize import brentq
+from scipy.special import xlogy
 
 
 def entropy(z) -> float:
@@ -31,7 +32,7 @@ def entropy(z) -> float:
     if z.size == 0:
         return 0.0
     p = z / z.sum()
-    return float(-np.sum(p * np.log(p)))
+    return float(-np.sum(xlogy(p, p)))     # 0 log 0 = 0 where a share underflows
 
 
 def power_normalised(z, beta):
