@@ -47,11 +47,12 @@ def flops_of(iters_total: int, n_pairs: int, d: int = D) -> float:
 
 
 def run_gpu(precision: str, steps: int, warmup: int, pts_d, off_d, switch_tol: float, gamma: float = GAMMA,
-            max_iter: int = 5000):
+            max_iter: int = 5000, kernel: str = "auto"):
     import torch
     import paper_1805_08331_amd as pds
 
-    ctx = pds.Context(D, gamma, tol=TOL, max_iter=max_iter, precision=precision, switch_tol=switch_tol)
+    ctx = pds.Context(D, gamma, tol=TOL, max_iter=max_iter, precision=precision, switch_tol=switch_tol,
+                      kernel=kernel)
     dev = ctx.device
     n = NPAIRS
     hist = torch.empty((2 * n, D, D), dtype=torch.float32, device=dev)
@@ -138,6 +139,69 @@ def cpu_baseline(budget_s: float = 20.0):
             "sample": f"benchmark batch (1024 pairs, d=100) pairs 0..{done - 1} ({its} pair-iterations, {t_used:.1f} s), FP64 dense "
                       f"(d^2+1)-point kernel on the host, cost matrix built once outside the timing; "
                       f"os.cpu_count()={os.cpu_count()}"}
+
+
+def cpu_separable(budget_s: float = 8.0, n_pairs: int = 3) -> dict:
+    """A second CPU figure: the same alternating iteration and stopping rule
+    with K applied in the separable form of Proposition 2, in the log domain
+    (FP64 NumPy; at gamma = 1e-3 the 1-D kernel entries underflow FP64, so
+    the scalings are kept as logarithms): log(K x) over the grid is two
+    log-sum-exp contractions over d, O(d^3) per half step, plus the diagonal
+    bin.  Not the oracle (which applies the dense (d^2+1)^2 kernel); timed on
+    the first pairs of the benchmark batch until ``budget_s``, iteration
+    counts reported to compare with the oracle's."""
+    import pdgen
+    from scipy.special import logsumexp
+
+    x = np.arange(D, dtype=np.float64)
+    G = -((np.abs(x[:, None] - x[None, :]) / D) ** 2) / GAMMA             # log k
+    GD = -2.0 * ((np.abs(x[None, :] - x[:, None]) / (2 * D)) ** 2) / GAMMA  # log k_Delta at cell (i, j)
+
+    def log_k(LX, lxd):
+        T = logsumexp(G[None, :, :] + LX[:, None, :], axis=2)      # T[k, j] = LSE_l G[j, l] + LX[k, l]
+        W = logsumexp(G[:, :, None] + T[None, :, :], axis=1)       # W[i, j] = LSE_k G[i, k] + T[k, j]
+        return np.logaddexp(W, lxd + GD), np.logaddexp(logsumexp(LX + GD), lxd)
+
+    def hist(pts):
+        h = np.zeros((D, D))
+        ij = np.minimum(np.floor(pts.astype(np.float64) * D).astype(np.int64), D - 1)
+        np.add.at(h, (ij[:, 0], ij[:, 1]), 1.0)
+        return h
+
+    d1, d2 = pdgen.pairs_batch(0, n_pairs)
+    its, t_used, counts = 0, 0.0, []
+    with np.errstate(divide="ignore", invalid="ignore"):
+        for q in range(n_pairs):
+            A, B = hist(d1[q]), hist(d2[q])
+            ma, mb = A.sum(), B.sum()
+            la, lb = np.log(A), np.log(B)
+            lad, lbd = np.log(mb), np.log(ma)                       # Proposition 1: a_Delta = |b|, b_Delta = |a|
+            m = ma + mb
+            LV, lvd = np.zeros((D, D)), 0.0
+            t0 = time.perf_counter()
+            done = False
+            for t in range(1, 5001):
+                KV, kvd = log_k(LV, lvd)
+                LU, lud = la - KV, lad - kvd
+                KU, kud = log_k(LU, lud)
+                LV, lvd = lb - KU, lbd - kud
+                KV2, kvd2 = log_k(LV, lvd)
+                err = (np.nansum(np.abs(np.exp(LU + KV2) - A)) + abs(np.exp(lud + kvd2) - mb)) / m
+                its += 1
+                if err <= TOL:
+                    done = True
+                    break
+                if t_used + time.perf_counter() - t0 >= budget_s:
+                    break
+            t_used += time.perf_counter() - t0
+            if done:
+                counts.append(t)
+            if t_used >= budget_s:
+                break
+    return {"value": its / t_used, "unit": "pair-it/s", "cores": 1, "kind": "cpu separable (log domain, FP64)",
+            "sample": f"benchmark batch from pair 0: {its} pair-iterations in {t_used:.1f} s, pairs run to "
+                      f"tol {TOL} took {counts} iterations (the oracle: 157, 495, 348); each iteration also "
+                      f"applies K once more for the error check"}
 
 
 def pmc_probe(pts_d, off_d, switch_tol: float, copy_mib: int = 256):
@@ -295,6 +359,45 @@ def gamma_sweep(pts_d, off_d, switch_tol: float):
                 "flagged": int(((st & 6) != 0).sum()), "max_iter": int(((st & 1) != 0).sum())}), flush=True)
 
 
+def scaling_study(n_pairs: int = 64, ns=(10, 20, 50, 100, 200, 500, 1000, 2000, 5000), max_iter: int = 40000):
+    """Distance time against diagram size at gamma_n = 0.1 / n (the scaling
+    experiment of section 5): for each n, ``n_pairs`` pairs of random diagrams
+    of n to 2n points, d = 100, BF16 contractions with FP32 refinement to
+    marginal error 1e-3 (pairs beyond the scaled representation's range go
+    to the log-domain path).  One JSON line per n, with the batch time, the
+    iteration quantiles, the paths the pairs took and t_n / t_10."""
+    import torch
+    import pdgen
+    import paper_1805_08331_amd as pds
+
+    t10 = None
+    for n in ns:
+        g = 0.1 / n
+        d1, d2 = pdgen.pairs_batch(n, n_pairs, n, 2 * n)
+        pts, off = pdgen.to_csr(d1 + d2)
+        with pds.Context(D, g, tol=TOL, max_iter=max_iter, precision="bf16", switch_tol=0.8e-3) as ctx:
+            hist, _, _ = pds.pd_discretize(ctx, torch.from_numpy(pts).cuda(), torch.from_numpy(off).cuda())
+            ia = torch.arange(0, n_pairs, dtype=torch.int32, device=hist.device)
+            ws = ctx.workspace(pds._lib.PDSINK_OP_DIST, n_pairs)
+            out = pds.sinkhorn_dist_batch(ctx, hist, hist, ia, ia + n_pairs, ws=ws)   # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pds.sinkhorn_dist_batch(ctx, hist, hist, ia, ia + n_pairs, out=out, ws=ws, check_indices=False)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            supp = (hist > 0).sum(dim=(1, 2)).cpu().numpy()
+        it = out.iters.sum(dim=1).cpu().numpy()
+        st = out.status.cpu().numpy()
+        t10 = ms if t10 is None else t10
+        print(json.dumps({
+            "n": n, "points": f"{n}-{2 * n}", "gamma": g, "gamma_d2": g * D * D, "pairs": n_pairs, "batch_ms": ms,
+            "ms_per_pair": ms / n_pairs, "t_over_t10": ms / t10,
+            "iters_p50": int(np.percentile(it, 50)), "iters_p99": int(np.percentile(it, 99)),
+            "support_max": int(supp.max()), "converged": int(((st & 7) == 0).sum()),
+            "log_path": int(((st & 8) != 0).sum()), "flagged": int(((st & 6) != 0).sum()),
+            "max_iter": int(((st & 1) != 0).sum())}), flush=True)
+
+
 def serve_bench(seconds: float, rate: float = 2000.0, k: int = 10, slots: int = 16, max_pairs: int = 512,
                 mem_budget: int = 64 << 30):
     """Serving loop on a Poisson stream: ``rate`` requests/s for ``seconds``
@@ -316,6 +419,22 @@ def serve_bench(seconds: float, rate: float = 2000.0, k: int = 10, slots: int = 
             h, _, _ = pds.pd_discretize(ctx, torch.from_numpy(pts).cuda(), torch.from_numpy(off).cuda())
             torch.cuda.synchronize()
             cents[d] = h.contiguous()
+    # tiling of each grid's distance kernel, timed on 256 pairs drawn like the
+    # stream's (the choice is cached for the server's contexts)
+    from paper_1805_08331_amd import autotune
+    tiling = {}
+    for d in grids:
+        if d not in autotune.RESIDENT_GRIDS:
+            tiling[str(d)] = {"kernel": "general (the only tiling at this grid)"}
+            continue
+        sd1, sd2 = pdgen.pairs_batch(100 + d, 256, 20, 600)
+        with pds.Context(d, GAMMA) as ctx:
+            pts, off = pdgen.to_csr(sd1 + sd2)
+            h, _, _ = pds.pd_discretize(ctx, torch.from_numpy(pts).cuda(), torch.from_numpy(off).cuda())
+        ia = torch.arange(0, 256, dtype=torch.int32, device=h.device)
+        t = autotune.tune_kernel(h, h, ia, ia + 256, d, GAMMA, TOL, precision="bf16", switch_tol=0.8e-3, reps=2)
+        tiling[str(d)] = {"kernel": t["kernel"], "median_ms": t["median_ms"]}
+    print(f"serve: kernel tiling {tiling}", file=sys.stderr, flush=True)
     srv = serve.Server(grids, GAMMA, centroids=cents, slots=slots, max_pairs=max_pairs, mem_budget=mem_budget,
                        tol=TOL, max_iter=5000, precision="bf16", switch_tol=0.8e-3)
     serve.run_stream(srv, pdgen.serve_stream(1, rate=rate, duration=1.0, grids=grids), timeout_s=120)
@@ -339,6 +458,7 @@ def serve_bench(seconds: float, rate: float = 2000.0, k: int = 10, slots: int = 
         "requests": len(reqs), "offered_req_per_s": rate, "duration_s": seconds,
         "served_req_per_s": len(reqs) / wall, "pairs_per_s": n_pairs / wall, "bad_status_pairs": bad, "log_path_pairs": log_path,
         "peak_device_bytes": srv.peak_bytes, "launches": n_launch, "by_grid": by_grid, "by_kind": by_kind,
+        "kernel_tiling": tiling,
         "config": {"workload": "Poisson stream, half distances and half k-means assignments (k resident "
                                "centroids), d uniform in {50, 100, 200}, lognormal(5, 0.7) points",
                    "k": k, "gamma": GAMMA, "tol": TOL, "slots": slots, "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"),
@@ -388,7 +508,7 @@ def serve_leg(seconds: float = 3.0, rate: float = 2000.0) -> dict:
     line = [x for x in r.stdout.splitlines() if x.startswith("{")][-1]
     rec = json.loads(line)
     return {k: rec[k] for k in ("p50_ms", "p99_ms", "max_ms", "requests", "offered_req_per_s", "served_req_per_s",
-                                "pairs_per_s", "bad_status_pairs", "by_grid", "config")}
+                                "pairs_per_s", "bad_status_pairs", "by_grid", "kernel_tiling", "config")}
 
 
 def main():
@@ -415,6 +535,8 @@ def main():
     ap.add_argument("--serve-hw-queues", type=int, default=16,
                     help="hardware queues of the process (GPU_MAX_HW_QUEUES, set before HIP starts; --serve)")
     ap.add_argument("--serve-max-pairs", type=int, default=512, help="pairs per launch at most (--serve)")
+    ap.add_argument("--scaling", action="store_true",
+                    help="distance time against diagram size n at gamma = 0.1 / n (n = 10 ... 5000), then exit")
     ap.add_argument("--bary", type=int, metavar="STEPS", default=None,
                     help="time STEPS outer steps of the barycenter workload, print its line, then exit")
     ap.add_argument("--no-extra", action="store_true",
@@ -454,6 +576,9 @@ def main():
     if args.bary is not None:
         print(json.dumps(bary_bench(args.bary)), flush=True)
         return
+    if args.scaling:
+        scaling_study()
+        return
     if args.phases:
         phase_profile(pts_d, off_d, args.switch_tol, args.phases)
         return
@@ -474,8 +599,22 @@ def main():
         return
 
     res = {}
+    # tiling of the distance kernel: timed on the benchmark batch itself, the
+    # faster one runs the timed steps (both solve the same iteration)
+    import paper_1805_08331_amd as pds
+    from paper_1805_08331_amd import autotune
+    with pds.Context(D, GAMMA) as ctx:
+        hist_t, _, _ = pds.pd_discretize(ctx, pts_d, off_d)
+    ia_t = torch.arange(0, NPAIRS, dtype=torch.int32, device=hist_t.device)
+    tuned = {}
     for prec in (["bf16", "fp32"] if args.only is None else [args.only]):
-        r = run_gpu(prec, args.steps, args.warmup, pts_d, off_d, args.switch_tol)
+        t = autotune.tune_kernel(hist_t, hist_t, ia_t, ia_t + NPAIRS, D, GAMMA, TOL, precision=prec,
+                                 switch_tol=args.switch_tol, reps=3)
+        tuned[prec] = {"kernel": t["kernel"], "median_ms": t["median_ms"], "cost_rel": t["cost_rel"]}
+        print(f"[{prec}] kernel tiling: {t['median_ms']} -> {t['kernel']}", file=sys.stderr, flush=True)
+    del hist_t
+    for prec in (["bf16", "fp32"] if args.only is None else [args.only]):
+        r = run_gpu(prec, args.steps, args.warmup, pts_d, off_d, args.switch_tol, kernel=tuned[prec]["kernel"])
         k_avg = float(np.mean(r["kernel_ms"])) / 1e3
         fl = flops_of(r["iters_total"], NPAIRS)
         r["pair_it_per_s"] = r["iters_total"] * args.steps / r["wall_s"]
@@ -529,7 +668,8 @@ def main():
                        "of": "one 1024-pair batch (discretise + Algorithm 1 + cost)"},
         "roofline": {"bound": "mfma", "achieved": m["achieved_tflops"], "peak": m["peak_tflops"], "unit": "TFLOP/s",
                      "frac": m["achieved_tflops"] / m["peak_tflops"], "traffic": measured_traffic(),
-                     "kernel": PAIR_KERNEL_NAME, "kernel_ms": k_avg * 1e3,
+                     "kernel": PAIR_KERNEL_NAME if tuned[main_key]["kernel"] == "resident" else "sinkhorn_pair_kernel",
+                     "kernel_ms": k_avg * 1e3,
                      "flops": "8 d^3 per pair-iteration + 8 d^3 per pair (cost), d = 100"},
     }
     if "peak_blend_tflops" in m:
@@ -548,6 +688,11 @@ def main():
         # BF16 refined to 1e-5 with the converged oracle)
         out["bf16_vs_fp32_cost_rel"] = {"max": float(rd.max()), "median": float(np.median(rd))}
     out["iterations_per_pair"] = m["iters_quantiles"]
+    out["kernel_tiling"] = {"choice": {k: v["kernel"] for k, v in tuned.items()},
+                            "median_ms": {k: v["median_ms"] for k, v in tuned.items()},
+                            "cost_rel_between": {k: v["cost_rel"] for k, v in tuned.items()},
+                            "candidates": "resident: K depth 16 ceil(d/16) = 112, BF16 kernels cached in LDS; "
+                                          "general: grid padded to 128, 32x32 tiles"}
     if not args.no_extra:
         print("barycenter leg", file=sys.stderr, flush=True)
         try:
@@ -558,6 +703,7 @@ def main():
         out["serving"] = serve_leg()
     if not args.no_cpu:
         oc, out["cpu_baseline"] = cpu_baseline()
+        out["cpu_separable"] = cpu_separable()
         n = len(oc)
         for key in res:
             dev = np.abs(res[key]["cost"][:n] - np.array(oc)) / np.abs(np.array(oc))

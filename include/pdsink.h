@@ -46,6 +46,20 @@ extern "C" {
 #define PDSINK_FP32        0  /* FP32 operands on MFMA, FP32 accumulation          */
 #define PDSINK_BF16_REFINE 1  /* BF16 operands until err <= switch_tol, then FP32  */
 
+/* Distance kernel of a context (pdsink_params.kernel).  Both compute the same
+ * iteration, stopping rule and cost (Algorithm 1, Propositions 2 and 3); they
+ * differ in tiling and padding.  The general kernel pads d to 32, 64, 128 or
+ * 256 and contracts over the padded grid; the resident kernel (grids 33 to
+ * 100) contracts over d rounded up to 16 and keeps the scaled kernels of both
+ * half steps in LDS between refits of the scales.  Pairs with a warm-start
+ * state, barycenter solves, bounds and pairs the resident kernel cannot hold
+ * (supports beyond 512 cells or below the diagonal) always run in the general
+ * kernel; a RESIDENT context below d = 65 pads the tables and those kernels to
+ * 128. */
+#define PDSINK_KERNEL_AUTO      0  /* resident for 65 <= d <= 100, general otherwise */
+#define PDSINK_KERNEL_RESIDENT  1  /* resident kernel; d in [33, 100], else PDSINK_EINVAL */
+#define PDSINK_KERNEL_GENERAL   2  /* general kernel at every d */
+
 /* Per-pair status bits written by sinkhorn_dist_batch / kmeans_assign. */
 #define PDSINK_ST_CONVERGED  0  /* err <= tol                                      */
 #define PDSINK_ST_MAX_ITER   1  /* stopped at max_iter with err > tol              */
@@ -65,6 +79,7 @@ typedef struct {
   int32_t precision;    /* PDSINK_FP32 or PDSINK_BF16_REFINE                           */
   double  switch_tol;   /* BF16_REFINE: switch to FP32 once err <= switch_tol (or after
                          * max_iter / 2 iterations); stopping is decided in FP32 only */
+  int32_t kernel;       /* PDSINK_KERNEL_*: tiling of the distance solves (0 = AUTO)   */
 } pdsink_params;
 
 /* Create a context for `params` on HIP device `device`: validates the
@@ -74,7 +89,8 @@ typedef struct {
  * (host) params, (host) out.  Returns PDSINK_EINVAL for d outside [2, 256],
  * p < 1, gamma < 1e-5 (the integer log2 scales of the iterates, about
  * 1.44 / gamma octaves, must stay far inside the int32 range the kernels
- * use), tol < 0, max_iter < 1 or an unknown precision. */
+ * use), tol < 0, max_iter < 1, an unknown precision or kernel, or
+ * PDSINK_KERNEL_RESIDENT outside d in [33, 100]. */
 int pdsink_ctx_create(const pdsink_params* params, int device, pdsink_ctx** out);
 
 /* Release the context's device tables.  NULL is a no-op. */
@@ -224,6 +240,21 @@ int pd_barycenter(pdsink_ctx* ctx, int64_t n_diag, const float* hist,
                   double lambda, int32_t max_outer, double energy_rtol, int32_t init_uniform,
                   float* z, double* energy, int32_t* outer,
                   void* ws, size_t ws_bytes, void* stream);
+
+/* Entropic sharpening of smoothed barycenters (section 4, the paragraph after
+ * Algorithm 2: the barycenters are smeared, and sharpening is the paper's
+ * pointer to more spiked ones).  For each histogram z[i] (d x d, in place),
+ * with M its mass and p = z[i] / M on its positive cells: if the Shannon
+ * entropy -sum p log p exceeds h0, z[i] <- M p^beta / sum p^beta with the
+ * beta > 1 at which that entropy equals h0 (FP64 bisection to adjacent
+ * doubles); if h0 <= log n_max, n_max the number of cells at the maximum,
+ * z[i] becomes M / n_max on those cells (beta = +inf, the limit).  Mass,
+ * support (but for the limit) and the order of the cells are kept.
+ *   z    (device) float32 [n, d, d] in/out
+ *   h0   target entropy in nats, finite and >= 0, else PDSINK_EINVAL
+ *   beta (device) double  [n] out, may be NULL: the exponent used (1 = unchanged)
+ * n = 0 is a no-op. */
+int pd_sharpen(pdsink_ctx* ctx, int64_t n, float* z, double h0, double* beta, void* stream);
 
 /* k-means assignment step (section 5): the distance of diagram n to centroid
  * c is the Algorithm 1 cost of (hist[n] + R z_c, z_c + R hist[n]); assign[n]

@@ -22,12 +22,14 @@ from . import _lib
 from ._lib import PdsinkError  # noqa: F401
 
 __all__ = ["Context", "pd_discretize", "sinkhorn_dist_batch", "sinkhorn_dist_batch_noalloc", "pd_barycenter",
-           "kmeans_assign",
-           "PdsinkError", "FP32", "BF16_REFINE"]
+           "kmeans_assign", "pd_sharpen", "PdsinkError", "FP32", "BF16_REFINE"]
 
 FP32 = _lib.PDSINK_FP32
 BF16_REFINE = _lib.PDSINK_BF16_REFINE
 _PREC = {"fp32": FP32, "bf16": BF16_REFINE, "bf16_refine": BF16_REFINE, FP32: FP32, BF16_REFINE: BF16_REFINE}
+# distance-kernel tiling: "auto" (the default per grid), "resident" (d in 33..100), "general"
+_KERNEL = {"auto": _lib.PDSINK_KERNEL_AUTO, "resident": _lib.PDSINK_KERNEL_RESIDENT,
+           "general": _lib.PDSINK_KERNEL_GENERAL, 0: 0, 1: 1, 2: 2}
 
 
 def _vp(t):
@@ -53,20 +55,21 @@ class Context:
     """A ``pdsink_ctx``: grid size, ground exponent, gamma and stopping rule."""
 
     def __init__(self, d: int, gamma: float, p: float = 2.0, tol: float = 1e-3, max_iter: int = 1000,
-                 precision="fp32", switch_tol: float = 1.5e-3, device=None):
+                 precision="fp32", switch_tol: float = 1.5e-3, device=None, kernel="auto"):
         lib = _lib.load()
         if device is None:
             device = torch.cuda.current_device()
         self.device_index = int(torch.device("cuda", device).index if not isinstance(device, int) else device)
         self.device = torch.device("cuda", self.device_index)
         prm = _lib.Params(int(d), float(p), float(gamma), float(tol), int(max_iter), _PREC[precision],
-                          float(switch_tol))
+                          float(switch_tol), _KERNEL[kernel])
         h = ctypes.c_void_p()
         _lib.check("pdsink_ctx_create", lib.pdsink_ctx_create(ctypes.byref(prm), self.device_index, ctypes.byref(h)))
         self._h = h
         self.d, self.gamma, self.p, self.tol, self.max_iter = int(d), float(gamma), float(p), float(tol), int(max_iter)
         self.precision = _PREC[precision]
         self.switch_tol = float(switch_tol)
+        self.kernel = _KERNEL[kernel]
 
     @property
     def handle(self):
@@ -210,6 +213,25 @@ def sinkhorn_dist_batch_noalloc(ctx: Context, hist_a: torch.Tensor, hist_b: torc
         ctx.handle, n, _vp(hist_a), _vp(hist_b), _vp(ia), _vp(ib), _vp(out.cost), _vp(out.iters),
         _vp(out.err), _vp(out.status), _stream()))
     return out
+
+
+def pd_sharpen(ctx: Context, z: torch.Tensor, h0: float, beta: torch.Tensor | None = None) -> torch.Tensor:
+    """Entropic sharpening of histograms ``z`` ([n, d, d] or [d, d] float32, in
+    place) to entropy ``h0`` (nats).  Returns the exponents used (float64 [n];
+    1 = unchanged, inf = the even split over the maximal cells)."""
+    dev = ctx.device
+    _need(z, "z", torch.float32, dev)
+    zz = z if z.dim() == 3 else z.unsqueeze(0)
+    if zz.dim() != 3 or zz.shape[1:] != (ctx.d, ctx.d):
+        raise ValueError(f"z must be [n, {ctx.d}, {ctx.d}] or [{ctx.d}, {ctx.d}]")
+    n = zz.shape[0]
+    if beta is None:
+        beta = torch.empty(n, dtype=torch.float64, device=dev)
+    _need(beta, "beta", torch.float64, dev)
+    if beta.numel() != n:
+        raise ValueError("beta needs one entry per histogram")
+    _lib.check("pd_sharpen", _lib.load().pd_sharpen(ctx.handle, n, _vp(zz), float(h0), _vp(beta), _stream()))
+    return beta
 
 
 def kmeans_assign(ctx: Context, hist: torch.Tensor, centroids: torch.Tensor, ws: torch.Tensor | None = None):

@@ -33,6 +33,7 @@ class Params(ctypes.Structure):
         ("max_iter", c_i32),
         ("precision", c_i32),
         ("switch_tol", c_dbl),
+        ("kernel", c_i32),
     ]
 
 
@@ -41,6 +42,10 @@ PDSINK_EINVAL = -1
 PDSINK_ENOMEM = -2
 PDSINK_EDEVICE = -3
 PDSINK_ERANGE = -4
+
+PDSINK_KERNEL_AUTO = 0
+PDSINK_KERNEL_RESIDENT = 1
+PDSINK_KERNEL_GENERAL = 2
 
 PDSINK_FP32 = 0
 PDSINK_BF16_REFINE = 1
@@ -73,6 +78,7 @@ SIGNATURES = {
                                            c_vp, c_vp, c_vp, c_size, c_vp]),
     "pd_barycenter": (c_int, [c_vp, c_i64, c_vp, c_dbl, c_i32, c_dbl, c_i32, c_vp,
                               ctypes.POINTER(c_dbl), ctypes.POINTER(c_i32), c_vp, c_size, c_vp]),
+    "pd_sharpen": (c_int, [c_vp, c_i64, c_vp, c_dbl, c_vp, c_vp]),
     "kmeans_assign": (c_int, [c_vp, c_i64, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_size, c_vp]),
     "pdsink_lloyd_workspace_bytes": (c_int, [c_vp, c_i64, c_i32, ctypes.POINTER(c_size)]),
     "kmeans_lloyd": (c_int, [c_vp, c_i64, c_vp, c_i32, c_vp, c_i32, c_dbl, c_i32, c_dbl, c_vp, c_vp, c_vp,

@@ -73,6 +73,15 @@ int scratch_lookup(int device, void** out) {
 
 int pad_grid(int d) { return d <= 32 ? 32 : (d <= 64 ? 64 : (d <= 128 ? 128 : 256)); }
 
+// Grids the resident-kernel variant takes (K depth 16 ceil(d / 16), 3 to 7
+// MFMA steps), and whether a context runs it: on request, or by default where
+// it measured faster than the general kernel.
+constexpr int RESIDENT_DMIN = 33;
+bool resident_for(int d, int kernel) {
+  if (d < RESIDENT_DMIN || d > FAST_DMAX) return false;
+  return kernel == PDSINK_KERNEL_RESIDENT || (kernel == PDSINK_KERNEL_AUTO && d >= RESIDENT_AUTO_DMIN);
+}
+
 struct DeviceGuard {
   int old = -1;
   bool ok = false;
@@ -252,16 +261,18 @@ int64_t slots_for(const pdsink_ctx* ctx, int64_t n_pairs) { return n_pairs < ctx
 // the same stream, with no host synchronisation; when no pair is flagged the
 // second launch only reads the flags.
 template <int D>
-int launch_levels(PairParams pp, int n_slots, hipStream_t st) {
+int launch_levels(PairParams pp, int n_slots, bool resident, hipStream_t st) {
   if (pp.upper || pp.lower) return launch_pair_bounds(D, pp, n_slots, st) ? PDSINK_EDEVICE : PDSINK_OK;
   pp.only_redo = 0;
   if constexpr (D == 128) {
     // Grids up to 100 without warm start or gradient output: the resident-kernel
     // variant; pairs it does not take (supports beyond 512 cells or below the
     // diagonal, suspect-list overflow) go to the global-list launch.
-    if (pp.d <= FAST_DMAX && !pp.state && !pp.gout) {
+    if (resident && !pp.state && !pp.gout) {
       const unsigned g = (unsigned)pp.n_pairs;
       switch ((pp.d + 15) / 16) {
+        case 3: hipLaunchKernelGGL(sinkhorn_fast_kernel<3>, dim3(g), dim3(PWGS), 0, st, pp); break;
+        case 4: hipLaunchKernelGGL(sinkhorn_fast_kernel<4>, dim3(g), dim3(PWGS), 0, st, pp); break;
         case 5: hipLaunchKernelGGL(sinkhorn_fast_kernel<5>, dim3(g), dim3(PWGS), 0, st, pp); break;
         case 6: hipLaunchKernelGGL(sinkhorn_fast_kernel<6>, dim3(g), dim3(PWGS), 0, st, pp); break;
         default: hipLaunchKernelGGL(sinkhorn_fast_kernel<7>, dim3(g), dim3(PWGS), 0, st, pp); break;
@@ -337,11 +348,12 @@ int run_pairs(const pdsink_ctx* ctx, int64_t n_pairs, const float* ha, const flo
     pp.perm = perm;
   }
   int rc;
+  const bool resident = ctx->D == 128 && resident_for(ctx->prm.d, ctx->prm.kernel);
   switch (ctx->D) {
-    case 32: rc = launch_levels<32>(pp, ex.n_slots, st); break;
-    case 64: rc = launch_levels<64>(pp, ex.n_slots, st); break;
-    case 128: rc = launch_levels<128>(pp, ex.n_slots, st); break;
-    default: rc = launch_levels<256>(pp, ex.n_slots, st); break;
+    case 32: rc = launch_levels<32>(pp, ex.n_slots, resident, st); break;
+    case 64: rc = launch_levels<64>(pp, ex.n_slots, resident, st); break;
+    case 128: rc = launch_levels<128>(pp, ex.n_slots, resident, st); break;
+    default: rc = launch_levels<256>(pp, ex.n_slots, resident, st); break;
   }
   if (rc || ex.state || ex.gout) return rc;
   // Pairs flagged NONFINITE or RANGE are solved again in the log domain (same
@@ -585,6 +597,89 @@ int warm_convert(int D, bool pack, double* state, const float* hist_b, const int
   }
 }
 
+// Entropic sharpening of histograms (pd_sharpen): histogram blockIdx.x of z,
+// one workgroup.  With l_c = log(z_c / max z) <= 0 on the positive cells, the
+// normalised power p^beta has entropy H(beta) = log Z - beta A / Z, where
+// Z = sum exp(beta l_c) and A = sum exp(beta l_c) l_c; H falls with beta from
+// the entropy of z at beta = 1 towards log n_max.  All in FP64 with
+// fixed-order reductions, so every thread takes the same branches; beta is
+// bracketed by doubling and found by bisection down to adjacent doubles.
+__global__ __launch_bounds__(WG) void sharpen_kernel(float* __restrict__ z, int dd, double h0,
+                                                     double* __restrict__ beta_out) {
+  __shared__ double red[NWAVE];
+  __shared__ int redi[NWAVE];
+  float* zn = z + (int64_t)blockIdx.x * dd;
+  const int tid = threadIdx.x;
+  double m = 0.0;
+  int zbits = 0;
+  for (int c = tid; c < dd; c += WG) {
+    const float v = zn[c];
+    if (v > 0.0f) {
+      m += (double)v;
+      zbits = max(zbits, __float_as_int(v));   // positive floats order as their bits
+    }
+  }
+  const double M = block_sum(m, red);
+  const float zmax = __int_as_float(block_max(zbits, redi));
+  if (!(M > 0.0)) {
+    if (tid == 0 && beta_out) beta_out[blockIdx.x] = 1.0;
+    return;
+  }
+  double cnt = 0.0;
+  for (int c = tid; c < dd; c += WG) cnt += zn[c] == zmax ? 1.0 : 0.0;
+  const double n_max = block_sum(cnt, red);
+  const double lmax = log((double)zmax);
+  auto sums = [&](double beta, double& Z, double& A) {
+    double zs = 0.0, as = 0.0;
+    for (int c = tid; c < dd; c += WG) {
+      const float v = zn[c];
+      if (v > 0.0f) {
+        const double l = log((double)v) - lmax;
+        const double w = exp(beta * l);
+        zs += w;
+        as += w * l;
+      }
+    }
+    Z = block_sum(zs, red);
+    A = block_sum(as, red);
+  };
+  auto entropy_at = [&](double beta) {
+    double Z, A;
+    sums(beta, Z, A);
+    return log(Z) - beta * A / Z;
+  };
+  double beta = 1.0;
+  if (entropy_at(1.0) <= h0) {
+    if (tid == 0 && beta_out) beta_out[blockIdx.x] = 1.0;
+    return;
+  }
+  if (h0 <= log(n_max)) {   // the limit: the mass evenly over the maximal cells
+    const float share = (float)(M / n_max);
+    for (int c = tid; c < dd; c += WG) zn[c] = zn[c] == zmax ? share : 0.0f;
+    if (tid == 0 && beta_out) beta_out[blockIdx.x] = INFINITY;
+    return;
+  }
+  double lo = 1.0, hi = 2.0;
+  while (entropy_at(hi) > h0 && hi < 0x1p60) {
+    lo = hi;
+    hi *= 2.0;
+  }
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (!(mid > lo && mid < hi)) break;
+    if (entropy_at(mid) > h0) lo = mid;
+    else hi = mid;
+  }
+  beta = 0.5 * (lo + hi);
+  double Z, A;
+  sums(beta, Z, A);
+  for (int c = tid; c < dd; c += WG) {
+    const float v = zn[c];
+    if (v > 0.0f) zn[c] = (float)(M * exp(beta * (log((double)v) - lmax)) / Z);
+  }
+  if (tid == 0 && beta_out) beta_out[blockIdx.x] = beta;
+}
+
 // sinkhorn_dist_batch and sinkhorn_dist_bounds_batch: the workspace is the
 // routing flags, the list slots, the launch order and (with `state`) the
 // scaled warm-start records.
@@ -638,11 +733,15 @@ int pdsink_ctx_create(const pdsink_params* params, int device, pdsink_ctx** out)
   const pdsink_params& p = *params;
   if (p.d < 2 || p.d > 256 || !(p.p >= 1.0) || !(p.gamma > 0.0) || !(p.tol >= 0.0) || p.max_iter < 1 ||
       (p.precision != PDSINK_FP32 && p.precision != PDSINK_BF16_REFINE) || !(p.switch_tol >= 0.0) ||
-      !std::isfinite(p.gamma) || !std::isfinite(p.p) || p.gamma < 1e-5)
+      !std::isfinite(p.gamma) || !std::isfinite(p.p) || p.gamma < 1e-5 || p.kernel < PDSINK_KERNEL_AUTO ||
+      p.kernel > PDSINK_KERNEL_GENERAL ||
+      (p.kernel == PDSINK_KERNEL_RESIDENT && (p.d < RESIDENT_DMIN || p.d > FAST_DMAX)))
     return PDSINK_EINVAL;
   DeviceGuard g(device);
   if (!g.ok) return PDSINK_EDEVICE;
-  const int D = pad_grid(p.d);
+  // The resident kernel reads the tables of the 128-padded layout: a context
+  // that runs it below d = 65 pads everything to 128.
+  const int D = resident_for(p.d, p.kernel) ? 128 : pad_grid(p.d);
   const int n = 2 * D - 1;
   std::vector<int> ge(n), gde(n);
   std::vector<float> gm(n), gdm(n), c1(n), cd(n);
@@ -800,6 +899,17 @@ int sinkhorn_dist_bounds_batch(pdsink_ctx* ctx, int64_t n_pairs, const float* hi
                                void* stream) {
   return dist_impl(ctx, n_pairs, hist_a, hist_b, ia, ib, nullptr, cost, iters, err, status, upper, lower, ws,
                    ws_bytes, stream);
+}
+
+int pd_sharpen(pdsink_ctx* ctx, int64_t n, float* z, double h0, double* beta, void* stream) {
+  if (!ctx || n < 0 || !(h0 >= 0.0) || !std::isfinite(h0)) return PDSINK_EINVAL;
+  if (n == 0) return PDSINK_OK;
+  if (!z || n > INT_MAX) return PDSINK_EINVAL;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return PDSINK_EDEVICE;
+  hipLaunchKernelGGL(sharpen_kernel, dim3((unsigned)n), dim3(WG), 0, (hipStream_t)stream, z,
+                     ctx->prm.d * ctx->prm.d, h0, beta);
+  return last_error();
 }
 
 int kmeans_assign(pdsink_ctx* ctx, int64_t n_diag, const float* hist, int32_t k, const float* centroids,

@@ -37,6 +37,7 @@ struct alignas(16) Src {
 };
 
 struct LogSmem {
+  static constexpr int cap = LOG_CAP;   // support cells per side the arrays hold
   Src src[2][LOG_CAP];      // side 0: a (u), side 1: b (v)
   double lt[2][LOG_CAP];    // log targets
   double lk[2][LOG_CAP];    // log of the latest K application at each cell
@@ -45,6 +46,22 @@ struct LogSmem {
   double red[LNW];
   int cnt[LWG];
   int n[2];
+};
+
+// The same lists in a global slice of the workspace slot (beyond the grid the
+// lower bound uses), for supports beyond LOG_CAP cells; the tables and the
+// reduction buffers stay in the workgroup's LDS.  The members mirror
+// LogSmem's, so the solve below is written once for both.
+struct LogGlobal {
+  int cap;
+  Src* src[2];
+  double* lt[2];
+  double* lk[2];
+  double* c1d;
+  double* cdd;
+  double* red;
+  int* cnt;
+  int* n;
 };
 
 __device__ __forceinline__ double block_max_d(double v, double* red) { return -block_min<LNW>(-v, red); }
@@ -69,7 +86,8 @@ __device__ __forceinline__ double lse2(double x, double y) {
 // Support list of one histogram, in cell order: counts per thread chunk, a
 // serial scan of the 512 counts, then each thread writes its chunk.  Returns
 // false (and leaves the list empty) when the support exceeds LOG_CAP.
-__device__ bool build_list(LogSmem& S, int side, const float* __restrict__ h, int d) {
+template <class SM>
+__device__ bool build_list(SM& S, int side, const float* __restrict__ h, int d) {
   const int n = d * d, per = (n + LWG - 1) / LWG;
   const int c0 = min((int)threadIdx.x * per, n), c1 = min(c0 + per, n);
   int k = 0;
@@ -87,7 +105,7 @@ __device__ bool build_list(LogSmem& S, int side, const float* __restrict__ h, in
   }
   __syncthreads();
   const int total = S.n[side];
-  if (total > LOG_CAP) return false;
+  if (total > S.cap) return false;
   int off = S.cnt[threadIdx.x];
   for (int c = c0; c < c1; ++c) {
     const float v = h[c];
@@ -104,8 +122,8 @@ __device__ bool build_list(LogSmem& S, int side, const float* __restrict__ h, in
 // LSE over the sources of side `src` (plus the diagonal-bin source xD) of
 // ls - C / gamma at grid cell (i, j); four sources per step.  P2: the ground
 // exponent is 2, so C = ((i - k)^2 + (j - l)^2) / d^2 without table reads.
-template <bool P2>
-__device__ __forceinline__ double lse_at(const LogSmem& S, int src, int i, int j, int d, double xD, double ig) {
+template <bool P2, class SM>
+__device__ __forceinline__ double lse_at(const SM& S, int src, int i, int j, int d, double xD, double ig) {
   const int ns = S.n[src];
   const Src* sr = S.src[src];
   const double* ci = S.c1d + i + d - 1;   // ci[-k] = c(i - k)
@@ -147,8 +165,8 @@ __device__ __forceinline__ double lse_at(const LogSmem& S, int src, int i, int j
 // The same log-sum-exp with SPLIT lanes per target cell (adjacent lanes of
 // a quad), each over every SPLIT-th source; the partial maxima and sums are
 // combined across the quad.  Every lane of the group returns the result.
-template <bool P2, int SPLIT>
-__device__ __forceinline__ double lse_split(const LogSmem& S, int src, int i, int j, int d, double xD, double ig,
+template <bool P2, int SPLIT, class SM>
+__device__ __forceinline__ double lse_split(const SM& S, int src, int i, int j, int d, double xD, double ig,
                                             int part) {
   const int ns = S.n[src];
   const Src* sr = S.src[src];
@@ -192,8 +210,8 @@ __device__ __forceinline__ double lse_split(const LogSmem& S, int src, int i, in
 // lk[tgt][e] = LSE over side `src` (plus the diagonal bin, log scaling xDb)
 // of ls - C / gamma at every cell e of side tgt: four lanes per cell when
 // the targets fit a quarter of the workgroup, two when they fit half.
-template <bool P2>
-__device__ void apply_lse(LogSmem& S, int tgt, int src, int d, double xDb, double ig) {
+template <bool P2, class SM>
+__device__ void apply_lse(SM& S, int tgt, int src, int d, double xDb, double ig) {
   const int nt = S.n[tgt], tid = threadIdx.x;
   if (nt <= LWG / 4) {
     const int t = tid >> 2, part = tid & 3;
@@ -219,7 +237,8 @@ __device__ void apply_lse(LogSmem& S, int tgt, int src, int d, double xDb, doubl
 
 // LSE over the sources of side `src` plus xD of ls - c_Delta / gamma: the
 // K application at the diagonal bin (C_Delta,Delta = 0).
-__device__ double lse_delta(LogSmem& S, int src, int d, double xD, double ig) {
+template <class SM>
+__device__ double lse_delta(SM& S, int src, int d, double xD, double ig) {
   const int n = S.n[src];
   double m = -INFINITY;
   for (int e = threadIdx.x; e < n; e += LWG) {
@@ -269,7 +288,8 @@ __device__ void log_minplus(double* g, const double* c1d, int d) {
   }
 }
 
-__device__ double log_lower_bound(LogSmem& S, double* g, int d, double gamma, double luD, double aD, double bD) {
+template <class SM>
+__device__ double log_lower_bound(SM& S, double* g, int d, double gamma, double luD, double aD, double bD) {
   const int tid = threadIdx.x, LG = d + 1;
   for (int c = tid; c < d * LG; c += LWG) g[c] = INFINITY;
   __syncthreads();
@@ -317,7 +337,8 @@ __device__ double log_lower_bound(LogSmem& S, double* g, int d, double gamma, do
 // Upper bound: on entry lk[0] holds log (K v) at the cells of supp(a) and
 // lkD0 at the diagonal bin, for the final (u, v).  The log scalings of both
 // sides are left scaled by X and Y.
-__device__ double log_upper_bound(LogSmem& S, int d, double ig, double luD, double lvD, double lkD0, double aD,
+template <class SM>
+__device__ double log_upper_bound(SM& S, int d, double ig, double luD, double lvD, double lkD0, double aD,
                                   double bD, bool p2) {
   const int tid = threadIdx.x;
   // X = min(a / r(P), 1) on u
@@ -381,7 +402,9 @@ __device__ double log_upper_bound(LogSmem& S, int d, double ig, double luD, doub
   return gs + (en > 0.0 ? tt / en : 0.0);
 }
 
-__device__ void solve_log_pair(const LogParams& prm, LogSmem& S, long long pair) {
+// Returns false, writing nothing, when a support does not fit S's lists.
+template <class SM>
+__device__ bool solve_log_pair(const LogParams& prm, SM& S, long long pair) {
   const int d = prm.d, tid = threadIdx.x;
   const double ig = 1.0 / prm.gamma;
   const bool p2 = prm.p == 2.0;
@@ -392,7 +415,7 @@ __device__ void solve_log_pair(const LogParams& prm, LogSmem& S, long long pair)
     S.c1d[x] = pow(dl / d, prm.p);
     S.cdd[x] = 2.0 * pow(dl / (2.0 * d), prm.p);
   }
-  if (!build_list(S, 0, A, d) || !build_list(S, 1, B, d)) return;   // stays flagged
+  if (!build_list(S, 0, A, d) || !build_list(S, 1, B, d)) return false;
   double ma = 0.0, mb = 0.0;
   for (int e = tid; e < S.n[0]; e += LWG) ma += exp(S.lt[0][e]);
   for (int e = tid; e < S.n[1]; e += LWG) mb += exp(S.lt[1][e]);
@@ -489,13 +512,40 @@ __device__ void solve_log_pair(const LogParams& prm, LogSmem& S, long long pair)
     if (prm.upper) prm.upper[pair] = up;
     if (prm.lower) prm.lower[pair] = lo;
   }
+  return true;
 }
 
 __global__ __launch_bounds__(LWG) void sinkhorn_log_kernel(LogParams prm) {
   __shared__ LogSmem S;
+  __shared__ LogGlobal G;   // in LDS, so that the solve's reference to it stays off the stack
+  if (threadIdx.x == 0) {
+    // the slot's global lists start after the grid of the lower bound
+    const size_t grid_bytes = ((size_t)8 * prm.d * (prm.d + 1) + 255) & ~(size_t)255;
+    char* slot = prm.scratch + (size_t)blockIdx.x * prm.scratch_stride;
+    const long long gcap =
+        prm.scratch_stride > grid_bytes ? (long long)((prm.scratch_stride - grid_bytes) / 64) : 0;
+    G.cap = (int)min(gcap, (long long)prm.d * prm.d);
+    char* base = slot + grid_bytes;
+    for (int side = 0; side < 2; ++side) {
+      G.src[side] = reinterpret_cast<Src*>(base + (size_t)side * G.cap * 16);
+      G.lt[side] = reinterpret_cast<double*>(base + (size_t)2 * G.cap * 16 + (size_t)side * G.cap * 8);
+      G.lk[side] = reinterpret_cast<double*>(base + (size_t)2 * G.cap * 24 + (size_t)side * G.cap * 8);
+    }
+    G.c1d = S.c1d;
+    G.cdd = S.cdd;
+    G.red = S.red;
+    G.cnt = S.cnt;
+    G.n = S.n;
+  }
+  __syncthreads();
   for (long long pair = blockIdx.x; pair < prm.n_pairs; pair += gridDim.x) {
     if (!(prm.status[pair] & 6)) continue;   // NONFINITE or RANGE
-    solve_log_pair(prm, S, pair);
+    // supports beyond the LDS lists take the global ones; beyond those the
+    // pair keeps its flags
+    if (!solve_log_pair(prm, S, pair) && G.cap > LOG_CAP) {
+      __syncthreads();
+      solve_log_pair(prm, G, pair);
+    }
     __syncthreads();
   }
 }

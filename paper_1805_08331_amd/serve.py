@@ -46,7 +46,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import torch
 
-from . import Context, _lib, kmeans_assign, pd_discretize, sinkhorn_dist_batch
+from . import Context, _lib, autotune, kmeans_assign, pd_discretize, sinkhorn_dist_batch
 
 DIST = 0
 ASSIGN = 1
@@ -139,7 +139,8 @@ class Server:
 
     def __init__(self, grids, gamma: float, centroids=None, slots: int = 4, max_pairs: int = 512,
                  mem_budget: int = 8 << 30, tol: float = 1e-3, max_iter: int = 5000,
-                 precision="bf16", switch_tol: float = 0.8e-3, device=None, clock=time.perf_counter):
+                 precision="bf16", switch_tol: float = 0.8e-3, device=None, clock=time.perf_counter,
+                 kernels=None):
         if slots < 1 or max_pairs < 1 or mem_budget < 1:
             raise ValueError("slots, max_pairs and mem_budget must be positive")
         if not grids:
@@ -155,9 +156,13 @@ class Server:
         self.mem_budget = int(mem_budget)
         self.clock = clock
         self.grids = {}
+        kernels = kernels or {}
         for d in grids:
+            # distance-kernel tiling: the caller's, else what autotune.tune_kernel
+            # chose for this grid and precision in this process, else the default
+            kern = kernels.get(d, autotune.choose_kernel(int(d), precision))
             ctx = Context(int(d), gamma, tol=tol, max_iter=max_iter, precision=precision, switch_tol=switch_tol,
-                          device=device)
+                          device=device, kernel=kern)
             cen = centroids.get(d)
             if cen is not None and (cen.dtype != torch.float32 or tuple(cen.shape[1:]) != (d, d)
                                     or cen.device != ctx.device or not cen.is_contiguous()):

@@ -62,6 +62,9 @@ def test_strerror_and_host_side_validation():
         _lib.Params(32, 2.0, 1e-3, -1.0, 100, 0, 1e-3),    # tol < 0
         _lib.Params(32, 2.0, 1e-3, 1e-3, 0, 0, 1e-3),      # max_iter < 1
         _lib.Params(32, 2.0, 1e-3, 1e-3, 100, 7, 1e-3),    # unknown precision
+        _lib.Params(64, 2.0, 1e-3, 1e-3, 100, 0, 1e-3, 7),   # unknown kernel
+        _lib.Params(32, 2.0, 1e-3, 1e-3, 100, 0, 1e-3, 1),   # resident kernel below its grids
+        _lib.Params(101, 2.0, 1e-3, 1e-3, 100, 0, 1e-3, 1),  # resident kernel above its grids
     ]
     for prm in bad:
         assert lib.pdsink_ctx_create(ctypes.byref(prm), 0, ctypes.byref(out)) == _lib.PDSINK_EINVAL

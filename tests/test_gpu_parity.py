@@ -190,6 +190,39 @@ def test_bf16_refine_against_converged(pds):
         assert rel(cost[q], r.cost) <= BF16_RTOL, (q, cost[q], r.cost)
 
 
+@pytest.mark.parametrize("d,g,lo,hi", [(40, 5e-3, 5, 80), (50, 1e-3, 20, 150), (64, 2e-3, 1, 60)])
+def test_resident_kernel_small_grids_same_schedule(pds, d, g, lo, hi):
+    """The resident kernel below the 128-padded class (K depth 48 and 64, on
+    the 128-padded tables): FP32 costs against the oracle run for the same
+    iteration count, and the stopping iteration within one of the oracle's."""
+    D1s, D2s = pdgen.pairs_batch(d, 12, lo, hi)
+    with pds.Context(d, g, tol=1e-4, max_iter=3000, kernel="resident") as ctx:
+        cost, iters, err, st, hist = run_pairs(pds, ctx, D1s, D2s)
+    C = dense_C(d)
+    for q in range(len(D1s)):
+        t = int(iters[q].sum())
+        r = sinkhorn.sinkhorn(hist[q], hist[len(D1s) + q], g, max_iter=t, C=C)
+        assert rel(cost[q], r.cost) <= FP32_RTOL, (q, cost[q], r.cost)
+        assert err[q] <= 1e-4 and st[q] == 0
+        ro = sinkhorn.sinkhorn(hist[q], hist[len(D1s) + q], g, tol=1e-4, max_iter=3000, C=C)
+        assert abs(ro.iters - t) <= 1
+
+
+def test_resident_kernel_bf16_small_grid_against_converged(pds):
+    """BF16 contractions in the resident kernel at d = 50 (3 x 16 = 48 < 50: four
+    MFMA steps), refined to 1e-5, against the converged FP64 fixed point."""
+    d, g = 50, 1e-3
+    D1s, D2s = pdgen.pairs_batch(3, 3, 20, 200)
+    with pds.Context(d, g, tol=1e-5, max_iter=20000, precision="bf16", switch_tol=1.5e-3,
+                     kernel="resident") as ctx:
+        cost, iters, err, st, hist = run_pairs(pds, ctx, D1s, D2s)
+    C = dense_C(d)
+    assert np.all(iters[:, 0] > 0) and np.all(st == 0)
+    for q in range(len(D1s)):
+        r = sinkhorn.sinkhorn(hist[q], hist[len(D1s) + q], g, tol=1e-7, max_iter=100000, C=C)
+        assert rel(cost[q], r.cost) <= BF16_RTOL, (q, cost[q], r.cost)
+
+
 def test_edge_cases(pds):
     """Empty diagrams (closed form: all mass to the diagonal), identical
     diagrams, single points, points on the border, d = 2 and d = 128."""
@@ -369,6 +402,27 @@ def test_tiny_gamma_same_schedule(pds, d, g, max_iter, log_path):
         ref = _log_oracle_cost(hist[q], hist[n + q], g, it, C)
         print(f"pair {q} status {st[q]} rel {rel(cost[q], ref):.2e}")
         assert rel(cost[q], ref) <= FP32_RTOL, (q, st[q], cost[q], ref)
+
+
+def test_log_path_large_supports(pds):
+    """Pairs whose supports exceed the log-domain path's LDS lists (1024 cells
+    per side: diagrams of 3000 to 4000 points at d = 64) are solved from lists
+    in the workspace slot, at gamma d^2 = 0.04 (every pair on the log path):
+    the cost after a fixed number of iterations against the log-sum-exp
+    oracle to 1e-5."""
+    d, g, it = 64, 1e-5, 40
+    D1s, D2s = pdgen.pairs_batch(17, 2, 3000, 4000)
+    C = dense_C(d)
+    with pds.Context(d, g, tol=0.0, max_iter=it) as ctx:
+        cost, iters, err, st, hist = run_pairs(pds, ctx, D1s, D2s)
+    n = len(D1s)
+    sizes = [(int(np.count_nonzero(hist[q])), int(np.count_nonzero(hist[n + q]))) for q in range(n)]
+    assert all(max(sz) > 1024 for sz in sizes), sizes
+    assert np.all(st == pds._lib.PDSINK_ST_LOG_PATH | pds._lib.PDSINK_ST_MAX_ITER), st
+    for q in range(n):
+        assert int(iters[q].sum()) == it
+        ref = _log_oracle_cost(hist[q], hist[n + q], g, it, C)
+        assert rel(cost[q], ref) <= FP32_RTOL, (q, sizes[q], cost[q], ref)
 
 
 def test_log_path_bounds_match_oracle(pds):
@@ -659,3 +713,46 @@ def test_barycenter_range_is_an_error(pds):
         with pytest.raises(pds.PdsinkError) as e:
             pds.pd_barycenter(ctx, H, lam=5.0, max_outer=3, energy_rtol=0.0)
         assert e.value.code == pds._lib.PDSINK_ERANGE
+
+
+@pytest.mark.parametrize("d", [16, 64, 200])
+def test_sharpen_matches_oracle(pds, d):
+    """Entropic sharpening of several histograms in one call against the FP64
+    oracle: a barycenter-like smooth histogram at three targets, an unchanged
+    one (target above its entropy), the limit (target below log n_max), a
+    uniform one and an empty one.  beta to 1e-12 relative, cells to 2e-6
+    (above the float32 denormals)."""
+    from oracle import sharpen
+    rng = np.random.default_rng(d)
+    i, j = np.indices((d, d))
+    smooth = np.where(j >= i, np.exp(-((i - d / 3) ** 2 + (j - d / 2) ** 2) / (0.05 * d * d)) + 0.05, 0.0)
+    noisy = np.where(j >= i, rng.gamma(0.6, 1.0, (d, d)), 0.0)
+    noisy[noisy < 0.05] = 0.0
+    ties = np.where(j >= i, 1.0, 0.0)
+    ties[0, 0] = ties[1, 1] = 3.0
+    zs = [smooth, smooth, smooth, noisy, ties, np.ones((d, d)), np.zeros((d, d))]
+    zs = [np.float32(z * 7.0) for z in zs]
+    h_s, h_n = sharpen.entropy(zs[0]), sharpen.entropy(zs[3])
+    h0 = 0.5 * h_s
+    targets = [h_s - 0.2, h0, 1.0, h_n + 0.1, np.log(2.0), 1.0, 1.0]
+    with pds.Context(d, 1e-2) as ctx:
+        # one call per target value (the target is per call)
+        for q, (z, t) in enumerate(zip(zs, targets)):
+            Z = torch.from_numpy(z.copy()).cuda()
+            beta = pds.pd_sharpen(ctx, Z, float(t))
+            torch.cuda.synchronize()
+            ref, rb = sharpen.sharpen(z.astype(np.float64), float(t))
+            b = float(beta.item())
+            if math.isinf(rb):
+                assert math.isinf(b), (q, b)
+            else:
+                assert abs(b - rb) <= 1e-12 * rb, (q, b, rb)
+            np.testing.assert_allclose(Z.cpu().numpy(), ref, rtol=2e-6, atol=1e-30)   # float32 denormals
+        # a batch of three with one target
+        Zb = torch.from_numpy(np.stack([zs[0], zs[3], zs[6]])).cuda().contiguous()
+        beta = pds.pd_sharpen(ctx, Zb, 1.5).cpu().numpy()
+        torch.cuda.synchronize()
+        for k, z in enumerate([zs[0], zs[3], zs[6]]):
+            ref, rb = sharpen.sharpen(z.astype(np.float64), 1.5)
+            assert (math.isinf(rb) and math.isinf(beta[k])) or abs(beta[k] - rb) <= 1e-12 * rb
+            np.testing.assert_allclose(Zb[k].cpu().numpy(), ref, rtol=2e-6, atol=1e-30)
