@@ -54,6 +54,7 @@ struct LogSmem {
 // LogSmem's, so the solve below is written once for both.
 struct LogGlobal {
   int cap;
+  Src* stage;     // LDS staging area of STAGE source entries (the unused LDS lists)
   Src* src[2];
   double* lt[2];
   double* lk[2];
@@ -231,6 +232,76 @@ __device__ void apply_lse(SM& S, int tgt, int src, int d, double xDb, double ig)
     for (int e = tid; e < nt; e += LWG) {
       const int c = S.src[tgt][e].cell, i = c >> 16, j = c & 0xFFFF;
       S.lk[tgt][e] = lse_at<P2>(S, src, i, j, d, xDb - S.cdd[j - i + d - 1] * ig, ig);
+    }
+  }
+}
+
+// apply_lse for lists in the workspace: the sources are staged through LDS
+// in chunks of STAGE entries, and each thread keeps TPT targets in registers,
+// so that one LDS read of a source serves TPT targets.  Per target a running
+// maximum and a sum scaled to it (the log-sum-exp taken in one pass per
+// chunk: the chunk's maximum, then its terms); the diagonal-bin source
+// starts the sum.  Targets beyond LWG * TPT take further rounds.
+constexpr int STAGE = 2 * LOG_CAP;
+constexpr int TPT = 8;
+template <bool P2>
+__device__ void apply_lse(LogGlobal& G, int tgt, int src, int d, double xDb, double ig) {
+  const int nt = G.n[tgt], ns = G.n[src], tid = threadIdx.x;
+  const double igd = ig / ((double)d * (double)d);
+  for (int r0 = 0; r0 < nt; r0 += LWG * TPT) {
+    int ti[TPT], tj[TPT];
+    double m[TPT], sm[TPT];
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+      const int t = r0 + tid + k * LWG;
+      const bool ok = t < nt;
+      const int c = ok ? G.src[tgt][t].cell : 0;
+      ti[k] = c >> 16;
+      tj[k] = c & 0xFFFF;
+      m[k] = ok ? xDb - G.cdd[tj[k] - ti[k] + d - 1] * ig : -INFINITY;   // the diagonal-bin source
+      sm[k] = ok ? 1.0 : 0.0;
+    }
+    for (int c0 = 0; c0 < ns; c0 += STAGE) {
+      const int nc = min(STAGE, ns - c0);
+      __syncthreads();
+      for (int e = tid; e < nc; e += LWG) G.stage[e] = G.src[src][c0 + e];
+      __syncthreads();
+      auto x_of = [&](const Src& q, int k) {
+        const int kk = q.cell >> 16, l = q.cell & 0xFFFF;
+        if constexpr (P2) {
+          const int di = ti[k] - kk, dj = tj[k] - l;
+          return q.ls - (double)(di * di + dj * dj) * igd;
+        } else {
+          return q.ls - (G.c1d[ti[k] - kk + d - 1] + G.c1d[tj[k] - l + d - 1]) * ig;
+        }
+      };
+      double cm[TPT];
+#pragma unroll
+      for (int k = 0; k < TPT; ++k) cm[k] = -INFINITY;
+      for (int e = 0; e < nc; ++e) {
+        const Src q = G.stage[e];
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) cm[k] = fmax(cm[k], x_of(q, k));
+      }
+      double cs[TPT];
+#pragma unroll
+      for (int k = 0; k < TPT; ++k) {
+        const double mn = fmax(m[k], cm[k]);
+        cs[k] = mn == -INFINITY ? 0.0 : sm[k] * exp_neg(m[k] - mn);
+        m[k] = mn;
+      }
+      for (int e = 0; e < nc; ++e) {
+        const Src q = G.stage[e];
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) cs[k] += exp_neg(x_of(q, k) - m[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < TPT; ++k) sm[k] = cs[k];
+    }
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+      const int t = r0 + tid + k * LWG;
+      if (t < nt) G.lk[tgt][t] = m[k] == -INFINITY ? -INFINITY : m[k] + log(sm[k]);
     }
   }
 }
@@ -515,45 +586,58 @@ __device__ bool solve_log_pair(const LogParams& prm, SM& S, long long pair) {
   return true;
 }
 
+// Pass 1 (GLOBAL = false): every flagged pair whose supports fit the LDS
+// lists.  Pass 2 (GLOBAL = true): the flagged pairs pass 1 left (no LOG_PATH
+// bit yet), from lists in the workspace slot; a pair beyond those keeps its
+// flags.  Two kernels, so that each gets its own register allocation.
+template <bool GLOBAL>
 __global__ __launch_bounds__(LWG) void sinkhorn_log_kernel(LogParams prm) {
   __shared__ LogSmem S;
-  __shared__ LogGlobal G;   // in LDS, so that the solve's reference to it stays off the stack
-  if (threadIdx.x == 0) {
-    // the slot's global lists start after the grid of the lower bound
-    const size_t grid_bytes = ((size_t)8 * prm.d * (prm.d + 1) + 255) & ~(size_t)255;
-    char* slot = prm.scratch + (size_t)blockIdx.x * prm.scratch_stride;
-    const long long gcap =
-        prm.scratch_stride > grid_bytes ? (long long)((prm.scratch_stride - grid_bytes) / 64) : 0;
-    G.cap = (int)min(gcap, (long long)prm.d * prm.d);
-    char* base = slot + grid_bytes;
-    for (int side = 0; side < 2; ++side) {
-      G.src[side] = reinterpret_cast<Src*>(base + (size_t)side * G.cap * 16);
-      G.lt[side] = reinterpret_cast<double*>(base + (size_t)2 * G.cap * 16 + (size_t)side * G.cap * 8);
-      G.lk[side] = reinterpret_cast<double*>(base + (size_t)2 * G.cap * 24 + (size_t)side * G.cap * 8);
-    }
-    G.c1d = S.c1d;
-    G.cdd = S.cdd;
-    G.red = S.red;
-    G.cnt = S.cnt;
-    G.n = S.n;
-  }
-  __syncthreads();
-  for (long long pair = blockIdx.x; pair < prm.n_pairs; pair += gridDim.x) {
-    if (!(prm.status[pair] & 6)) continue;   // NONFINITE or RANGE
-    // supports beyond the LDS lists take the global ones; beyond those the
-    // pair keeps its flags
-    if (!solve_log_pair(prm, S, pair) && G.cap > LOG_CAP) {
+  if constexpr (!GLOBAL) {
+    for (long long pair = blockIdx.x; pair < prm.n_pairs; pair += gridDim.x) {
+      if (!(prm.status[pair] & 6)) continue;   // NONFINITE or RANGE
+      solve_log_pair(prm, S, pair);
       __syncthreads();
-      solve_log_pair(prm, G, pair);
+    }
+  } else {
+    __shared__ LogGlobal G;   // in LDS, so that the solve's reference to it stays off the stack
+    if (threadIdx.x == 0) {
+      // the slot's global lists start after the grid of the lower bound
+      const size_t grid_bytes = ((size_t)8 * prm.d * (prm.d + 1) + 255) & ~(size_t)255;
+      char* slot = prm.scratch + (size_t)blockIdx.x * prm.scratch_stride;
+      const long long gcap =
+          prm.scratch_stride > grid_bytes ? (long long)((prm.scratch_stride - grid_bytes) / 64) : 0;
+      G.cap = (int)min(gcap, (long long)prm.d * prm.d);
+      char* base = slot + grid_bytes;
+      for (int side = 0; side < 2; ++side) {
+        G.src[side] = reinterpret_cast<Src*>(base + (size_t)side * G.cap * 16);
+        G.lt[side] = reinterpret_cast<double*>(base + (size_t)2 * G.cap * 16 + (size_t)side * G.cap * 8);
+        G.lk[side] = reinterpret_cast<double*>(base + (size_t)2 * G.cap * 24 + (size_t)side * G.cap * 8);
+      }
+      G.stage = &S.src[0][0];
+      G.c1d = S.c1d;
+      G.cdd = S.cdd;
+      G.red = S.red;
+      G.cnt = S.cnt;
+      G.n = S.n;
     }
     __syncthreads();
+    if (G.cap <= LOG_CAP) return;
+    for (long long pair = blockIdx.x; pair < prm.n_pairs; pair += gridDim.x) {
+      const int st = prm.status[pair];
+      if (!(st & 6) || (st & ST_LOG)) continue;   // unflagged, or solved by pass 1
+      solve_log_pair(prm, G, pair);
+      __syncthreads();
+    }
   }
 }
 
 }  // namespace
 
 int launch_log_path(const LogParams& lp, int n_slots, hipStream_t st) {
-  hipLaunchKernelGGL(sinkhorn_log_kernel, dim3((unsigned)n_slots), dim3(LWG), 0, st, lp);
+  hipLaunchKernelGGL(sinkhorn_log_kernel<false>, dim3((unsigned)n_slots), dim3(LWG), 0, st, lp);
+  if (hipGetLastError() != hipSuccess) return -1;
+  hipLaunchKernelGGL(sinkhorn_log_kernel<true>, dim3((unsigned)n_slots), dim3(LWG), 0, st, lp);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -475,6 +475,24 @@ __device__ __forceinline__ bool kt_tile(int w, int u, bool tri, int& ti, int& tj
   return true;
 }
 
+// The same over a grid of nt x nt tiles (nt known at run time).
+__device__ __forceinline__ bool kt_tile_n(int w, int u, bool tri, int nt, int& ti, int& tj) {
+  int tile = w + u * PNW;
+  if (!tri) {
+    ti = tile / nt;
+    tj = tile % nt;
+    return tile < nt * nt;
+  }
+  if (tile >= nt * (nt + 1) / 2) return false;
+  ti = 0;
+  while (tile >= nt - ti) {
+    tile -= nt - ti;
+    ++ti;
+  }
+  tj = ti + tile;
+  return true;
+}
+
 // Contraction 1 of Proposition 2 for the calling wave's tiles (tk, tj):
 //   T[k][j] = sum_l X[k][l] * kt2[j][l]   (kt2 times c1 when WEIGHTED: the m of Prop. 3)
 // With `trim`, X is zero below the diagonal and l starts at the tile's first row.
@@ -769,10 +787,15 @@ __device__ __forceinline__ void gemm_kt(PairSmem<D>& s, const int* P, float* Wb,
 
 // The contractions for grids beyond 128 (operands in the global slice): one
 // tile at a time per wave, tiles w, w + 8, ...; the K x buffer has its own
-// storage, so each tile is stored as soon as it is done.
+// storage, so each tile is stored as soon as it is done.  Only the tiles that
+// hold rows or columns below d are computed, and the depth runs to d rounded
+// up to 16: X is zero beyond its d columns and the kernels beyond d rows, and
+// nothing reads T or W beyond the tiles of the grid (d = 200: 49 of 64 tiles
+// at depth 208 of 256).
 template <int D, bool BF16, bool WEIGHTED>
-__device__ __forceinline__ void gemm_xk_g(PairSmem<D>& s, const int* Q, bool trim) {
-  constexpr int NT = Cfg<D>::NT, LDF = Cfg<D>::LDF, LDB = Cfg<D>::LDB;
+__device__ __forceinline__ void gemm_xk_g(PairSmem<D>& s, const int* Q, bool trim, int d) {
+  constexpr int LDF = Cfg<D>::LDF, LDB = Cfg<D>::LDB;
+  const int NT = (d + 31) >> 5, KD = (d + 15) & ~15;
   const int lane = threadIdx.x & 63, lr = lane & 31, lk = lane >> 5;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (int tile = w; tile < NT * NT; tile += PNW) {
@@ -784,7 +807,7 @@ __device__ __forceinline__ void gemm_xk_g(PairSmem<D>& s, const int* Q, bool tri
       const __bf16* xa = opXb<D>(s) + row * LDB + 8 * lk;
       const __bf16* kb = opK2b<D>(s) + j * LDB + 8 * lk;
 #pragma unroll 2
-      for (int l0 = lbeg; l0 < D; l0 += 16) {
+      for (int l0 = lbeg; l0 < KD; l0 += 16) {
         const bf16x8 a = *reinterpret_cast<const bf16x8*>(xa + l0);
         const bf16x8 b = *reinterpret_cast<const bf16x8*>(kb + l0);
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
@@ -797,7 +820,7 @@ __device__ __forceinline__ void gemm_xk_g(PairSmem<D>& s, const int* Q, bool tri
       const int Sj = s.S[j];
       const float* X = opXf<D>(s);
 #pragma unroll 4
-      for (int l0 = lbeg; l0 < D; l0 += 2) {
+      for (int l0 = lbeg; l0 < KD; l0 += 2) {
         const int l = l0 + lk;
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(X[row * LDF + l], kentry<D, WEIGHTED>(s, j, l, Q, Sj), acc, 0, 0,
                                                    0);
@@ -811,19 +834,20 @@ __device__ __forceinline__ void gemm_xk_g(PairSmem<D>& s, const int* Q, bool tri
 }
 
 template <int D, bool BF16, bool WEIGHTED>
-__device__ __forceinline__ void gemm_kt_g(PairSmem<D>& s, const int* P, float* Wb, bool tri) {
+__device__ __forceinline__ void gemm_kt_g(PairSmem<D>& s, const int* P, float* Wb, bool tri, int d) {
   constexpr int LDF = Cfg<D>::LDF, LDB = Cfg<D>::LDB;
+  const int NT = (d + 31) >> 5, KD = (d + 15) & ~15;
   const int lane = threadIdx.x & 63, lr = lane & 31, lk = lane >> 5;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int ti, tj;
-  for (int u = 0; kt_tile<D>(w, u, tri, ti, tj); ++u) {
+  for (int u = 0; kt_tile_n(w, u, tri, NT, ti, tj); ++u) {
     const int i = ti * 32 + lr, j = tj * 32 + lr;
     floatx16 acc = {};
     if constexpr (BF16) {
       const __bf16* ka = opK1b<D>(s) + i * LDB + 8 * lk;
       const __bf16* tb = opTtb<D>(s) + j * LDB + 8 * lk;
 #pragma unroll 2
-      for (int k0 = 0; k0 < D; k0 += 16) {
+      for (int k0 = 0; k0 < KD; k0 += 16) {
         const bf16x8 a = *reinterpret_cast<const bf16x8*>(ka + k0);
         const bf16x8 b = *reinterpret_cast<const bf16x8*>(tb + k0);
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
@@ -832,7 +856,7 @@ __device__ __forceinline__ void gemm_kt_g(PairSmem<D>& s, const int* P, float* W
       const int Ri = s.R[i];
       const float* T = opTf<D>(s);
 #pragma unroll 4
-      for (int k0 = 0; k0 < D; k0 += 2) {
+      for (int k0 = 0; k0 < KD; k0 += 2) {
         const int k = k0 + lk;
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(kentry<D, WEIGHTED>(s, i, k, P, Ri), T[k * LDF + j], acc, 0, 0, 0);
       }
@@ -846,15 +870,16 @@ __device__ __forceinline__ void gemm_kt_g(PairSmem<D>& s, const int* P, float* W
 
 // Contractions of one K application (LDS or global operands).
 template <int D, bool BF16, bool WEIGHTED1, bool WEIGHTED2>
-__device__ __forceinline__ void contract(PairSmem<D>& s, const int* P, const int* Q, float* Wb, bool trim, bool tri) {
+__device__ __forceinline__ void contract(PairSmem<D>& s, const int* P, const int* Q, float* Wb, bool trim, bool tri,
+                                         int d) {
   if constexpr (D <= 128) {
     gemm_xk<D, BF16, WEIGHTED1>(s, Q, trim);
     __syncthreads();
     gemm_kt<D, BF16, WEIGHTED2>(s, P, Wb, tri);
   } else {
-    gemm_xk_g<D, BF16, WEIGHTED1>(s, Q, trim);
+    gemm_xk_g<D, BF16, WEIGHTED1>(s, Q, trim, d);
     __syncthreads();
-    gemm_kt_g<D, BF16, WEIGHTED2>(s, P, Wb, tri);
+    gemm_kt_g<D, BF16, WEIGHTED2>(s, P, Wb, tri, d);
   }
 }
 
@@ -880,9 +905,9 @@ __device__ __forceinline__ float* apply_K(PairSmem<D>& s, const int* P, const in
   if (lowp) {
     build_kernels_bf16<D>(s, d);
     __syncthreads();
-    contract<D, true, false, false>(s, P, Q, Wb, trim, tri);
+    contract<D, true, false, false>(s, P, Q, Wb, trim, tri, d);
   } else {
-    contract<D, false, false, false>(s, P, Q, Wb, trim, tri);
+    contract<D, false, false, false>(s, P, Q, Wb, trim, tri, d);
   }
   return Wb;
 }
@@ -1992,8 +2017,8 @@ __device__ __forceinline__ void solve_pair(const PairParams& prm, PairSmem<D>& s
   double g = 0.0;
   float* Wf = wbuf<D>(s, false);
   for (int pass = 0; pass < 2; ++pass) {
-    if (pass == 0) contract<D, false, false, true>(s, s.Pv, s.Qv, Wf, tri && !v_dense, tri);
-    else contract<D, false, true, false>(s, s.Pv, s.Qv, Wf, tri && !v_dense, tri);
+    if (pass == 0) contract<D, false, false, true>(s, s.Pv, s.Qv, Wf, tri && !v_dense, tri, d);
+    else contract<D, false, true, false>(s, s.Pv, s.Qv, Wf, tri && !v_dense, tri, d);
 #pragma unroll
     for (int k = 0; k < nka; ++k) {
       const int c = ua.cell(k);

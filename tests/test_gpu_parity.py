@@ -576,10 +576,13 @@ def test_kmeans_lloyd_matches_oracle(pds):
         np.testing.assert_allclose(zc[c], cents[c], rtol=1e-4, atol=1e-6 * cents[c].max())
 
 
-def test_graph_capture_replays(pds):
+@pytest.mark.parametrize("d", [64, 100])
+def test_graph_capture_replays(pds, d):
     """The distance launches captured in a HIP graph: every replay, with eager
-    work and synchronisations between replays, equals the eager run bitwise."""
-    d, g, n = 64, 2e-3, 16
+    work and synchronisations between replays, equals the eager run bitwise
+    (d = 64: the general kernel; d = 100: the resident kernel and, for the
+    supports beyond 512 cells, the global-list launch)."""
+    g, n = 2e-3, 16
     D1s, D2s = pdgen.pairs_batch(12, n, 5, 2500)
     with pds.Context(d, g, tol=1e-4, max_iter=3000, precision="bf16") as ctx:
         pts, off = pdgen.to_csr(list(D1s) + list(D2s))
