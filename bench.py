@@ -47,7 +47,7 @@ def flops_of(iters_total: int, n_pairs: int, d: int = D) -> float:
 
 
 def run_gpu(precision: str, steps: int, warmup: int, pts_d, off_d, switch_tol: float, gamma: float = GAMMA,
-            max_iter: int = 5000, kernel: str = "auto"):
+            max_iter: int = 5000, kernel: str = "auto", graph: bool = False):
     import torch
     import paper_1805_08331_amd as pds
 
@@ -93,6 +93,35 @@ def run_gpu(precision: str, steps: int, warmup: int, pts_d, off_d, switch_tol: f
     status = out.status.cpu().numpy()
     cost = out.cost.cpu().numpy()
     err = out.err.cpu().numpy()
+    graph_rec = None
+    if graph:
+        # the same step (discretise + solve) captured once in a HIP graph and
+        # replayed: every replay must give the eager step's results bit for bit
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            step()
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        same = True
+        gms = []
+        for _ in range(max(steps, 3)):
+            out.cost.fill_(-1.0)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            g.replay()
+            e1.record(stream)
+            e1.synchronize()
+            gms.append(e0.elapsed_time(e1))
+            same = same and np.array_equal(out.cost.cpu().numpy(), cost) and \
+                np.array_equal(out.iters.cpu().numpy().astype(np.int64), iters)
+        graph_rec = {"ms_per_step": float(np.median(gms)), "replays": len(gms), "equal_to_eager": bool(same),
+                     "of": "discretise + Algorithm 1 + cost, one HIP graph per step"}
+        del g
     ctx.close()
     it_total = int(iters.sum())
     return {
@@ -109,6 +138,7 @@ def run_gpu(precision: str, steps: int, warmup: int, pts_d, off_d, switch_tol: f
         "cost": cost,
         "iters_q": {"p50": int(np.percentile(iters.sum(axis=1), 50)),
                     "p99": int(np.percentile(iters.sum(axis=1), 99))},
+        "graph": graph_rec,
     }
 
 
@@ -359,13 +389,17 @@ def gamma_sweep(pts_d, off_d, switch_tol: float):
                 "flagged": int(((st & 6) != 0).sum()), "max_iter": int(((st & 1) != 0).sum())}), flush=True)
 
 
-def scaling_study(n_pairs: int = 64, ns=(10, 20, 50, 100, 200, 500, 1000, 2000, 5000), max_iter: int = 40000):
+def scaling_study(n_pairs: int = 64, ns=(10, 20, 50, 100, 200, 500, 1000, 2000, 5000), max_iter: int = 40000,
+                  large_pairs: int = 16):
     """Distance time against diagram size at gamma_n = 0.1 / n (the scaling
     experiment of section 5): for each n, ``n_pairs`` pairs of random diagrams
     of n to 2n points, d = 100, BF16 contractions with FP32 refinement to
     marginal error 1e-3 (pairs beyond the scaled representation's range go
     to the log-domain path).  One JSON line per n, with the batch time, the
-    iteration quantiles, the paths the pairs took and t_n / t_10."""
+    iteration quantiles, the paths the pairs took and t_n / t_10.  From
+    n = 1000 on the batch has ``large_pairs`` pairs (they run side by side, so
+    the batch time is that of its slowest pair); only the first n has an
+    untimed warm-up launch."""
     import torch
     import pdgen
     import paper_1805_08331_amd as pds
@@ -373,16 +407,18 @@ def scaling_study(n_pairs: int = 64, ns=(10, 20, 50, 100, 200, 500, 1000, 2000, 
     t10 = None
     for n in ns:
         g = 0.1 / n
-        d1, d2 = pdgen.pairs_batch(n, n_pairs, n, 2 * n)
+        npairs = n_pairs if n < 1000 else large_pairs
+        print(f"scaling: n = {n}, {npairs} pairs", file=sys.stderr, flush=True)
+        d1, d2 = pdgen.pairs_batch(n, npairs, n, 2 * n)
         pts, off = pdgen.to_csr(d1 + d2)
         with pds.Context(D, g, tol=TOL, max_iter=max_iter, precision="bf16", switch_tol=0.8e-3) as ctx:
             hist, _, _ = pds.pd_discretize(ctx, torch.from_numpy(pts).cuda(), torch.from_numpy(off).cuda())
-            ia = torch.arange(0, n_pairs, dtype=torch.int32, device=hist.device)
-            ws = ctx.workspace(pds._lib.PDSINK_OP_DIST, n_pairs)
-            out = pds.sinkhorn_dist_batch(ctx, hist, hist, ia, ia + n_pairs, ws=ws)   # warm-up
+            ia = torch.arange(0, npairs, dtype=torch.int32, device=hist.device)
+            ws = ctx.workspace(pds._lib.PDSINK_OP_DIST, npairs)
+            out = pds.sinkhorn_dist_batch(ctx, hist, hist, ia, ia + npairs, ws=ws) if t10 is None else None
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            pds.sinkhorn_dist_batch(ctx, hist, hist, ia, ia + n_pairs, out=out, ws=ws, check_indices=False)
+            out = pds.sinkhorn_dist_batch(ctx, hist, hist, ia, ia + npairs, out=out, ws=ws, check_indices=False)
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) * 1e3
             supp = (hist > 0).sum(dim=(1, 2)).cpu().numpy()
@@ -390,12 +426,63 @@ def scaling_study(n_pairs: int = 64, ns=(10, 20, 50, 100, 200, 500, 1000, 2000, 
         st = out.status.cpu().numpy()
         t10 = ms if t10 is None else t10
         print(json.dumps({
-            "n": n, "points": f"{n}-{2 * n}", "gamma": g, "gamma_d2": g * D * D, "pairs": n_pairs, "batch_ms": ms,
-            "ms_per_pair": ms / n_pairs, "t_over_t10": ms / t10,
+            "n": n, "points": f"{n}-{2 * n}", "gamma": g, "gamma_d2": g * D * D, "pairs": npairs, "batch_ms": ms,
+            "ms_per_pair": ms / npairs, "t_over_t10": ms / t10,
             "iters_p50": int(np.percentile(it, 50)), "iters_p99": int(np.percentile(it, 99)),
             "support_max": int(supp.max()), "converged": int(((st & 7) == 0).sum()),
             "log_path": int(((st & 8) != 0).sum()), "flagged": int(((st & 6) != 0).sum()),
             "max_iter": int(((st & 1) != 0).sum())}), flush=True)
+
+
+def kmeans_bench(rounds: int = 2, n_diag: int = 4000, k: int = 10, d: int = 100, gamma: float = GAMMA,
+                 max_outer: int = 10):
+    """The k-means workload: ``n_diag`` diagrams drawn around 10 templates of
+    200 points (jitter 0.03, +-20 % points), k = 10, d = 100, BF16 with FP32
+    refinement to marginal error 1e-3.  Lloyd rounds run through the binding's
+    calls (assignment of all n_diag x k pairs, then the barycenter of each
+    cluster's members from the uniform start, at most ``max_outer`` outer
+    steps, energy rtol 0.01), one JSON line per round with its timings."""
+    import torch
+    import pdgen
+    import paper_1805_08331_amd as pds
+
+    diags, labels = pdgen.kmeans_set(0, n_diag)
+    pts, off = pdgen.to_csr(diags)
+    init = np.random.default_rng(0).choice(n_diag, size=k, replace=False)
+    with pds.Context(d, gamma, tol=TOL, max_iter=5000, precision="bf16", switch_tol=0.8e-3) as ctx:
+        hist, _, _ = pds.pd_discretize(ctx, torch.from_numpy(pts).cuda(), torch.from_numpy(off).cuda())
+        cents = hist[torch.from_numpy(init).cuda().long()].contiguous()
+        ws = ctx.workspace(pds._lib.PDSINK_OP_KMEANS, n_diag * k)
+        for r in range(rounds):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            assign, dist, st = pds.kmeans_assign(ctx, hist, cents, ws=ws)
+            torch.cuda.synchronize()
+            t_assign = time.perf_counter() - t0
+            a = assign.cpu().numpy()
+            obj = float(dist.cpu().numpy()[np.arange(n_diag), a].sum())
+            t1 = time.perf_counter()
+            outer = []
+            for c in range(k):
+                members = np.nonzero(a == c)[0]
+                if members.size == 0:
+                    continue
+                z, _, n_out = pds.pd_barycenter(ctx, hist[torch.from_numpy(members).cuda().long()].contiguous(),
+                                                lam=5.0, max_outer=max_outer, energy_rtol=0.01)
+                cents[c] = z
+                outer.append(n_out)
+            torch.cuda.synchronize()
+            t_bary = time.perf_counter() - t1
+            # purity: the share of diagrams in the majority template of their cluster
+            purity = sum(int(np.bincount(labels[a == c], minlength=k).max()) for c in range(k) if np.any(a == c))
+            purity /= n_diag
+            print(json.dumps({
+                "round": r, "assign_s": t_assign, "assign_pairs_per_s": n_diag * k / t_assign,
+                "barycenters_s": t_bary, "outer_steps": outer, "objective": obj,
+                "bad_status": int(np.count_nonzero(st.cpu().numpy() & 6)),
+                "purity": purity,
+                "workload": f"{n_diag} diagrams, k={k}, d={d}, gamma={gamma}, BF16 + FP32 refinement, tol {TOL}"}),
+                flush=True)
 
 
 def serve_bench(seconds: float, rate: float = 2000.0, k: int = 10, slots: int = 16, max_pairs: int = 512,
@@ -535,6 +622,8 @@ def main():
     ap.add_argument("--serve-hw-queues", type=int, default=16,
                     help="hardware queues of the process (GPU_MAX_HW_QUEUES, set before HIP starts; --serve)")
     ap.add_argument("--serve-max-pairs", type=int, default=512, help="pairs per launch at most (--serve)")
+    ap.add_argument("--kmeans", type=int, metavar="ROUNDS", default=None,
+                    help="Lloyd rounds of the k-means workload (4000 diagrams, k = 10, d = 100), then exit")
     ap.add_argument("--scaling", action="store_true",
                     help="distance time against diagram size n at gamma = 0.1 / n (n = 10 ... 5000), then exit")
     ap.add_argument("--bary", type=int, metavar="STEPS", default=None,
@@ -579,6 +668,9 @@ def main():
     if args.scaling:
         scaling_study()
         return
+    if args.kmeans is not None:
+        kmeans_bench(args.kmeans)
+        return
     if args.phases:
         phase_profile(pts_d, off_d, args.switch_tol, args.phases)
         return
@@ -614,7 +706,8 @@ def main():
         print(f"[{prec}] kernel tiling: {t['median_ms']} -> {t['kernel']}", file=sys.stderr, flush=True)
     del hist_t
     for prec in (["bf16", "fp32"] if args.only is None else [args.only]):
-        r = run_gpu(prec, args.steps, args.warmup, pts_d, off_d, args.switch_tol, kernel=tuned[prec]["kernel"])
+        r = run_gpu(prec, args.steps, args.warmup, pts_d, off_d, args.switch_tol, kernel=tuned[prec]["kernel"],
+                    graph=prec == "bf16")
         k_avg = float(np.mean(r["kernel_ms"])) / 1e3
         fl = flops_of(r["iters_total"], NPAIRS)
         r["pair_it_per_s"] = r["iters_total"] * args.steps / r["wall_s"]
@@ -688,6 +781,8 @@ def main():
         # BF16 refined to 1e-5 with the converged oracle)
         out["bf16_vs_fp32_cost_rel"] = {"max": float(rd.max()), "median": float(np.median(rd))}
     out["iterations_per_pair"] = m["iters_quantiles"]
+    if m.get("graph"):
+        out["graph_replay"] = m["graph"]
     out["kernel_tiling"] = {"choice": {k: v["kernel"] for k, v in tuned.items()},
                             "median_ms": {k: v["median_ms"] for k, v in tuned.items()},
                             "cost_rel_between": {k: v["cost_rel"] for k, v in tuned.items()},
