@@ -435,13 +435,16 @@ def scaling_study(n_pairs: int = 64, ns=(10, 20, 50, 100, 200, 500, 1000, 2000, 
 
 
 def kmeans_bench(rounds: int = 2, n_diag: int = 4000, k: int = 10, d: int = 100, gamma: float = GAMMA,
-                 max_outer: int = 10):
+                 max_outer: int = 10, sharpen: bool = False):
     """The k-means workload: ``n_diag`` diagrams drawn around 10 templates of
     200 points (jitter 0.03, +-20 % points), k = 10, d = 100, BF16 with FP32
     refinement to marginal error 1e-3.  Lloyd rounds run through the binding's
     calls (assignment of all n_diag x k pairs, then the barycenter of each
     cluster's members from the uniform start, at most ``max_outer`` outer
-    steps, energy rtol 0.01), one JSON line per round with its timings."""
+    steps, energy rtol 0.01), one JSON line per round with its timings.
+    ``sharpen``: each barycenter is then sharpened (pd_sharpen) to the mean
+    entropy of its members' histograms, the use the paper suggests for its
+    smeared barycenters."""
     import torch
     import pdgen
     import paper_1805_08331_amd as pds
@@ -467,8 +470,13 @@ def kmeans_bench(rounds: int = 2, n_diag: int = 4000, k: int = 10, d: int = 100,
                 members = np.nonzero(a == c)[0]
                 if members.size == 0:
                     continue
-                z, _, n_out = pds.pd_barycenter(ctx, hist[torch.from_numpy(members).cuda().long()].contiguous(),
-                                                lam=5.0, max_outer=max_outer, energy_rtol=0.01)
+                mh = hist[torch.from_numpy(members).cuda().long()].contiguous()
+                z, _, n_out = pds.pd_barycenter(ctx, mh, lam=5.0, max_outer=max_outer, energy_rtol=0.01)
+                if sharpen:
+                    p = mh.reshape(members.size, -1).double().cpu().numpy()
+                    p = p / p.sum(axis=1, keepdims=True)
+                    h0 = float(np.mean(-np.sum(np.where(p > 0, p * np.log(np.where(p > 0, p, 1.0)), 0.0), axis=1)))
+                    pds.pd_sharpen(ctx, z, h0)
                 cents[c] = z
                 outer.append(n_out)
             torch.cuda.synchronize()
@@ -480,7 +488,7 @@ def kmeans_bench(rounds: int = 2, n_diag: int = 4000, k: int = 10, d: int = 100,
                 "round": r, "assign_s": t_assign, "assign_pairs_per_s": n_diag * k / t_assign,
                 "barycenters_s": t_bary, "outer_steps": outer, "objective": obj,
                 "bad_status": int(np.count_nonzero(st.cpu().numpy() & 6)),
-                "purity": purity,
+                "purity": purity, "sharpened": sharpen,
                 "workload": f"{n_diag} diagrams, k={k}, d={d}, gamma={gamma}, BF16 + FP32 refinement, tol {TOL}"}),
                 flush=True)
 
@@ -624,6 +632,8 @@ def main():
     ap.add_argument("--serve-max-pairs", type=int, default=512, help="pairs per launch at most (--serve)")
     ap.add_argument("--kmeans", type=int, metavar="ROUNDS", default=None,
                     help="Lloyd rounds of the k-means workload (4000 diagrams, k = 10, d = 100), then exit")
+    ap.add_argument("--kmeans-sharpen", action="store_true",
+                    help="with --kmeans: sharpen each barycenter to its members' mean entropy")
     ap.add_argument("--scaling", action="store_true",
                     help="distance time against diagram size n at gamma = 0.1 / n (n = 10 ... 5000), then exit")
     ap.add_argument("--bary", type=int, metavar="STEPS", default=None,
@@ -669,7 +679,7 @@ def main():
         scaling_study()
         return
     if args.kmeans is not None:
-        kmeans_bench(args.kmeans)
+        kmeans_bench(args.kmeans, sharpen=args.kmeans_sharpen)
         return
     if args.phases:
         phase_profile(pts_d, off_d, args.switch_tol, args.phases)
