@@ -230,8 +230,10 @@ int sinkhorn_dist_bounds_batch(pdsink_ctx* ctx, int64_t n_pairs,
  *            otherwise overwritten with the uniform measure on cells j >= i of
  *            total mass = mean diagram mass; on return, z_t.
  *   energy   (host)   double out, E_t;  outer (host) int32 out, t
- * This call synchronises `stream` between outer steps (the stopping test is on
- * the host).  n_diag >= 1.  PDSINK_ERANGE when an inner solve ends with
+ * The outer steps are all enqueued on `stream` at once: the energy and the
+ * stopping test run on the device, and the launches of the steps after the
+ * stop do nothing; the call synchronises `stream` once, at the end, to read
+ * the energy and the step count.  n_diag >= 1.  PDSINK_ERANGE when an inner solve ends with
  * PDSINK_ST_NONFINITE or PDSINK_ST_RANGE (its iterates left the scaled
  * representation, gamma d^2 of order 1 or below): the energy and the step
  * would then be wrong, and these warm-started solves do not take the
@@ -282,7 +284,8 @@ int kmeans_assign(pdsink_ctx* ctx, int64_t n_diag, const float* hist,
  *   objective (host)   double  [rounds]   out, may be NULL: per round, the sum over
  *             the diagrams of the distance to the assigned centroid
  *   ws, ws_bytes (device) at least pdsink_lloyd_workspace_bytes(n_diag, k)
- * Synchronises `stream` once per round and per barycenter outer step.
+ * Synchronises `stream` once per round (its assignment) and once per
+ * barycenter.
  * PDSINK_ERANGE if a distance or barycenter step is not finite. */
 int pdsink_lloyd_workspace_bytes(const pdsink_ctx* ctx, int64_t n_diag, int32_t k, size_t* bytes);
 int kmeans_lloyd(pdsink_ctx* ctx, int64_t n_diag, const float* hist, int32_t k, const int32_t* init,

@@ -234,6 +234,7 @@ struct PairExtras {
   int n_slots = 0;            // workgroup slots (grid of the global-list variant)
   char* state = nullptr;      // WarmState per pair
   int state_in = 0;
+  const int* stop = nullptr;  // device flag: the solve launches do nothing when set
   double* gout = nullptr;     // [n_pairs][d * d] gradient terms
   double* upper = nullptr;    // [n_pairs] error-control bounds
   double* lower = nullptr;
@@ -326,6 +327,7 @@ int run_pairs(const pdsink_ctx* ctx, int64_t n_pairs, const float* ha, const flo
   pp.state = ex.state;
   pp.state_in = ex.state_in;
   pp.gout = ex.gout;
+  pp.stop = ex.stop;
   pp.upper = ex.upper;
   pp.lower = ex.lower;
   pp.gamma = ctx->prm.gamma;
@@ -440,9 +442,64 @@ __global__ void bary_uniform_kernel(const double* mass, int64_t n, int d, float*
   z[c] = j >= i ? (float)(m / (0.5 * d * (d + 1))) : 0.0f;
 }
 
+// Device state of the barycenter's outer loop: the host enqueues every outer
+// step, and the stopping test of Algorithm 2 runs on the device.
+struct BaryCtl {
+  int stop;       // set once the loop has ended: later launches do nothing
+  int err;        // an inner solve left the scaled range (PDSINK_ERANGE)
+  int outer;      // outer steps taken
+  int pad;
+  double energy;  // E_t of the last step taken
+  double prev;    // E_{t-1}
+};
+
+__global__ void bary_ctl_init_kernel(BaryCtl* ctl) {
+  if (threadIdx.x == 0) {
+    ctl->stop = 0;
+    ctl->err = 0;
+    ctl->outer = 0;
+    ctl->pad = 0;
+    ctl->energy = 0.0;
+    ctl->prev = 0.0;
+  }
+}
+
+// Energy of outer step t (Algorithm 2: the mean of the pairs' Sinkhorn costs,
+// summed in a fixed order) and the stopping test: relative change below
+// rtol, or the last step.  A solve that left the scaled range (NONFINITE or
+// RANGE) stops the loop with the error flag: z keeps the last good iterate.
+__global__ __launch_bounds__(WG) void bary_energy_kernel(const double* __restrict__ cost,
+                                                         const int32_t* __restrict__ st, int64_t n, int t,
+                                                         int max_outer, double rtol, BaryCtl* ctl) {
+  __shared__ double red[NWAVE];
+  __shared__ int redi[NWAVE];
+  if (ctl->stop) return;
+  double sum = 0.0;
+  int bad = 0;
+  for (int64_t q = threadIdx.x; q < n; q += WG) {
+    sum += cost[q];
+    bad |= (st[q] & (PDSINK_ST_NONFINITE | PDSINK_ST_RANGE)) != 0;
+  }
+  sum = block_sum(sum, red);
+  bad = block_max(bad, redi);
+  if (threadIdx.x != 0) return;
+  if (bad) {
+    ctl->err = 1;
+    ctl->stop = 1;
+    return;
+  }
+  const double E = sum / (double)n;
+  ctl->energy = E;
+  ctl->outer = t + 1;
+  if ((t > 0 && fabs(E / ctl->prev - 1.0) < rtol) || t == max_outer - 1) ctl->stop = 1;
+  else ctl->prev = E;
+}
+
 // Multiplicative step of Algorithm 2 on the support of z, gradient summed
-// over the diagrams in a fixed order.
-__global__ void bary_step_kernel(const double* __restrict__ gout, int64_t n, int d, double scale, float* z) {
+// over the diagrams in a fixed order (nothing once the loop has stopped).
+__global__ void bary_step_kernel(const double* __restrict__ gout, int64_t n, int d, double scale, float* z,
+                                 const BaryCtl* __restrict__ ctl) {
+  if (ctl->stop) return;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= d * d) return;
   const float zc = z[c];
@@ -837,7 +894,8 @@ int pdsink_workspace_bytes(const pdsink_ctx* ctx, int op, int64_t n_items, size_
     case PDSINK_OP_BARYCENTER:   // the KMEANS arrays for n pairs, warm states, gradient terms
       *bytes = align256(n_items * 4) * 2 + align256(n_items * 8) + align256(n_items * 8) + align256(n_items * 4) * 2 +
                align256(n_items) + slots_for(ctx, n_items) * slot_bytes(ctx->D) +
-               align256(n_items * warm_bytes(ctx->D)) + align256(n_items * 8 * (size_t)ctx->prm.d * ctx->prm.d);
+               align256(n_items * warm_bytes(ctx->D)) + align256(n_items * 8 * (size_t)ctx->prm.d * ctx->prm.d) +
+               256;   // the outer loop's device state
       return PDSINK_OK;
     default: return PDSINK_EINVAL;
   }
@@ -1002,37 +1060,29 @@ int pd_barycenter(pdsink_ctx* ctx, int64_t n_diag, const float* hist, double lam
     hipLaunchKernelGGL(bary_uniform_kernel, dim3((unsigned)((d * d + 255) / 256)), dim3(256), 0, s, cost, N, d, z);
     if ((rc = last_error())) return rc;
   }
-  std::vector<double> hc(N);
-  std::vector<int32_t> hs(N);
-  double E = 0.0, E_prev = 0.0;
-  int t = 0;
-  for (t = 0; t < max_outer; ++t) {
+  // Every outer step is enqueued at once; the energy kernel of step t runs the
+  // stopping test on the device, and the launches after it do nothing.  One
+  // synchronisation at the end reads the result.
+  BaryCtl* ctl = reinterpret_cast<BaryCtl*>(ex.gout + (size_t)N * d * d);
+  ex.stop = &ctl->stop;
+  hipLaunchKernelGGL(bary_ctl_init_kernel, dim3(1), dim3(64), 0, s, ctl);
+  if ((rc = last_error())) return rc;
+  for (int t = 0; t < max_outer; ++t) {
     ex.state_in = t > 0;
     rc = run_pairs(ctx, N, z, hist, ia, ib, cost, iters, err, st, redo, ex, s);
     if (rc) return rc;
-    if (hipMemcpyAsync(hc.data(), cost, N * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(hs.data(), st, N * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return PDSINK_EDEVICE;
-    double sum = 0.0;
-    for (int64_t q = 0; q < N; ++q) {
-      // A solve whose scaled iterates left the representable range (the log
-      // domain path does not serve the barycenter's warm-started solves) would
-      // feed a wrong cost and gradient into the step: refuse it.
-      if (hs[q] & (PDSINK_ST_NONFINITE | PDSINK_ST_RANGE)) return PDSINK_ERANGE;
-      sum += hc[q];
-    }
-    E = sum / (double)N;
-    if (t > 0 && std::fabs(E / E_prev - 1.0) < energy_rtol) break;
-    if (t == max_outer - 1) break;
+    hipLaunchKernelGGL(bary_energy_kernel, dim3(1), dim3(WG), 0, s, cost, st, N, t, max_outer, energy_rtol, ctl);
     // z <- z exp(-lambda grad), grad = (gamma / N) sum_i (log u_i + log v_i,Delta)  (Proposition 5)
     hipLaunchKernelGGL(bary_step_kernel, dim3((unsigned)((d * d + 255) / 256)), dim3(256), 0, s, ex.gout, N, d,
-                       lambda * ctx->prm.gamma / (double)N, z);
+                       lambda * ctx->prm.gamma / (double)N, z, ctl);
     if ((rc = last_error())) return rc;
-    E_prev = E;
   }
-  *energy = E;
-  *outer = t + 1;
+  BaryCtl h;
+  if (hipMemcpyAsync(&h, ctl, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+    return PDSINK_EDEVICE;
+  if (h.err) return PDSINK_ERANGE;
+  *energy = h.energy;
+  *outer = h.outer;
   return PDSINK_OK;
 }
 

@@ -91,6 +91,9 @@ struct PairParams {
   // optional gradient terms of Proposition 5, [n_pairs][d * d]: log u + log
   // v_Delta on the cells of supp(a)
   double* gout;
+  // optional device flag: when it is set the launch does nothing (the
+  // barycenter's outer steps after its stopping test)
+  const int* stop;
   // optional error-control bounds of section 3 per pair (upper: rounded plan,
   // lower: c-transform dual), with the ground exponent and gamma they need
   double* upper;
@@ -2126,6 +2129,7 @@ __device__ __forceinline__ void solve_pair(const PairParams& prm, PairSmem<D>& s
 template <int D, int SPT, bool BOUNDS = false>
 __global__ __launch_bounds__(PWGS) void sinkhorn_pair_kernel(PairParams prm) {
   __shared__ PairSmem<D> s;
+  if (prm.stop && *prm.stop) return;
   if constexpr (SPT > 0 && D <= 128) {   // one pair per workgroup
     const long long pair = prm.perm ? prm.perm[blockIdx.x] : blockIdx.x;
     if (prm.only_redo && prm.redo[pair] != prm.only_redo) return;
