@@ -66,3 +66,13 @@ def sharpen(z, h0: float):
         hi *= 2.0
     beta = brentq(f, 1.0, hi, xtol=1e-14, rtol=4 * np.finfo(float).eps, maxiter=500)
     return power_normalised(z, beta), float(beta)
+
+
+def quantize(z) -> np.ndarray:
+    """Quantisation of a barycenter to point counts (the paper's other pointer
+    to spikier barycenters, with no formula; reading taken here): each cell's
+    mass, in point units, rounded to the nearest integer, halves upwards
+    (floor(z + 1/2), exact for float32 input).  The result is a histogram of
+    integer counts, that is a persistence diagram on the grid."""
+    z = np.asarray(z, np.float64)
+    return np.floor(z + 0.5).astype(np.int64)

@@ -555,3 +555,18 @@ def test_sharpen_no_op_and_limits():
     zs, beta = sharpen.sharpen(u, 1.0)
     np.testing.assert_allclose(zs, u)
     assert sharpen.sharpen(np.zeros((2, 2)), 0.5)[1] == 1.0
+
+
+def test_quantize_rounds_each_cell_to_counts():
+    """Integer counts nearest to each cell's mass, halves upwards; an integer
+    histogram is a fixed point; the total stays within half a point per
+    positive cell of the mass."""
+    from oracle import sharpen
+    z = np.array([[0.49, 0.5, 1.5], [0.0, 2.49999, 3.0], [0.0, 0.0, 7.51]], np.float32)
+    q = sharpen.quantize(z)
+    np.testing.assert_array_equal(q, [[0, 1, 2], [0, 2, 3], [0, 0, 8]])
+    h = np.array([[2.0, 0.0], [1.0, 5.0]], np.float32)
+    np.testing.assert_array_equal(sharpen.quantize(h), h.astype(np.int64))
+    rng = np.random.default_rng(2)
+    r = np.float32(rng.gamma(0.5, 2.0, (20, 20)))
+    assert abs(int(sharpen.quantize(r).sum()) - float(r.sum())) <= 0.5 * np.count_nonzero(r)
