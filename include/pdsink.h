@@ -258,6 +258,17 @@ int pd_barycenter(pdsink_ctx* ctx, int64_t n_diag, const float* hist,
  * n = 0 is a no-op. */
 int pd_sharpen(pdsink_ctx* ctx, int64_t n, float* z, double h0, double* beta, void* stream);
 
+/* Quantisation of smoothed barycenters to point counts (section 4, the
+ * paragraph after Algorithm 2: quantisation is the paper's other pointer to
+ * spikier barycenters; reading: each cell's mass, in point units, rounded to
+ * the nearest integer, halves upwards).  q may alias z; the result is a
+ * histogram of integer counts (a diagram on the grid) that the other calls
+ * take as any histogram.
+ *   z (device) float32 [n, d, d]
+ *   q (device) float32 [n, d, d] out: floor(z + 1/2), exact
+ * n = 0 is a no-op. */
+int pd_quantize(pdsink_ctx* ctx, int64_t n, const float* z, float* q, void* stream);
+
 /* k-means assignment step (section 5): the distance of diagram n to centroid
  * c is the Algorithm 1 cost of (hist[n] + R z_c, z_c + R hist[n]); assign[n]
  * is the index of the smallest distance, ties to the lowest index.

@@ -22,7 +22,7 @@ from . import _lib
 from ._lib import PdsinkError  # noqa: F401
 
 __all__ = ["Context", "pd_discretize", "sinkhorn_dist_batch", "sinkhorn_dist_batch_noalloc", "pd_barycenter",
-           "kmeans_assign", "pd_sharpen", "PdsinkError", "FP32", "BF16_REFINE"]
+           "kmeans_assign", "pd_sharpen", "pd_quantize", "PdsinkError", "FP32", "BF16_REFINE"]
 
 FP32 = _lib.PDSINK_FP32
 BF16_REFINE = _lib.PDSINK_BF16_REFINE
@@ -232,6 +232,23 @@ def pd_sharpen(ctx: Context, z: torch.Tensor, h0: float, beta: torch.Tensor | No
         raise ValueError("beta needs one entry per histogram")
     _lib.check("pd_sharpen", _lib.load().pd_sharpen(ctx.handle, n, _vp(zz), float(h0), _vp(beta), _stream()))
     return beta
+
+
+def pd_quantize(ctx: Context, z: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Histograms ``z`` ([n, d, d] or [d, d] float32) rounded cell by cell to
+    point counts (float32 integers); ``out`` may be ``z`` itself."""
+    dev = ctx.device
+    _need(z, "z", torch.float32, dev)
+    if z.shape[-2:] != (ctx.d, ctx.d) or z.dim() not in (2, 3):
+        raise ValueError(f"z must be [n, {ctx.d}, {ctx.d}] or [{ctx.d}, {ctx.d}]")
+    if out is None:
+        out = torch.empty_like(z)
+    _need(out, "out", torch.float32, dev)
+    if out.shape != z.shape:
+        raise ValueError("out must have the shape of z")
+    n = 1 if z.dim() == 2 else z.shape[0]
+    _lib.check("pd_quantize", _lib.load().pd_quantize(ctx.handle, n, _vp(z), _vp(out), _stream()))
+    return out
 
 
 def kmeans_assign(ctx: Context, hist: torch.Tensor, centroids: torch.Tensor, ws: torch.Tensor | None = None):

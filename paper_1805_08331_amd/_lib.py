@@ -79,6 +79,7 @@ SIGNATURES = {
     "pd_barycenter": (c_int, [c_vp, c_i64, c_vp, c_dbl, c_i32, c_dbl, c_i32, c_vp,
                               ctypes.POINTER(c_dbl), ctypes.POINTER(c_i32), c_vp, c_size, c_vp]),
     "pd_sharpen": (c_int, [c_vp, c_i64, c_vp, c_dbl, c_vp, c_vp]),
+    "pd_quantize": (c_int, [c_vp, c_i64, c_vp, c_vp, c_vp]),
     "kmeans_assign": (c_int, [c_vp, c_i64, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_size, c_vp]),
     "pdsink_lloyd_workspace_bytes": (c_int, [c_vp, c_i64, c_i32, ctypes.POINTER(c_size)]),
     "kmeans_lloyd": (c_int, [c_vp, c_i64, c_vp, c_i32, c_vp, c_i32, c_dbl, c_i32, c_dbl, c_vp, c_vp, c_vp,

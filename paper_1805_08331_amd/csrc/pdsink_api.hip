@@ -737,6 +737,13 @@ __global__ __launch_bounds__(WG) void sharpen_kernel(float* __restrict__ z, int 
   if (tid == 0 && beta_out) beta_out[blockIdx.x] = beta;
 }
 
+// Quantisation of histograms to point counts: each cell rounded to the
+// nearest integer, halves upwards, in FP64 from the float32 value (exact).
+__global__ void quantize_kernel(const float* __restrict__ z, int64_t total, float* __restrict__ q) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < total) q[c] = (float)floor((double)z[c] + 0.5);
+}
+
 // sinkhorn_dist_batch and sinkhorn_dist_bounds_batch: the workspace is the
 // routing flags, the list slots, the launch order and (with `state`) the
 // scaled warm-start records.
@@ -967,6 +974,19 @@ int pd_sharpen(pdsink_ctx* ctx, int64_t n, float* z, double h0, double* beta, vo
   if (!g.ok) return PDSINK_EDEVICE;
   hipLaunchKernelGGL(sharpen_kernel, dim3((unsigned)n), dim3(WG), 0, (hipStream_t)stream, z,
                      ctx->prm.d * ctx->prm.d, h0, beta);
+  return last_error();
+}
+
+int pd_quantize(pdsink_ctx* ctx, int64_t n, const float* z, float* q, void* stream) {
+  if (!ctx || n < 0) return PDSINK_EINVAL;
+  if (n == 0) return PDSINK_OK;
+  if (!z || !q) return PDSINK_EINVAL;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return PDSINK_EDEVICE;
+  const int64_t total = n * (int64_t)ctx->prm.d * ctx->prm.d;
+  if (total / 256 + 1 > (int64_t)UINT_MAX) return PDSINK_EINVAL;
+  hipLaunchKernelGGL(quantize_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, (hipStream_t)stream, z,
+                     total, q);
   return last_error();
 }
 

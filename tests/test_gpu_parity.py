@@ -759,3 +759,30 @@ def test_sharpen_matches_oracle(pds, d):
             ref, rb = sharpen.sharpen(z.astype(np.float64), 1.5)
             assert (math.isinf(rb) and math.isinf(beta[k])) or abs(beta[k] - rb) <= 1e-12 * rb
             np.testing.assert_allclose(Zb[k].cpu().numpy(), ref, rtol=2e-6, atol=1e-30)
+
+
+def test_quantize_bit_exact(pds):
+    """Quantisation to point counts equals the oracle's cell by cell, bit for
+    bit, on a barycenter of the library (d = 40) sharpened first (smeared
+    over 820 cells its 50-odd points of mass round to nothing), and on hand
+    values at the rounding boundaries; in place as well."""
+    from oracle import sharpen
+    d, g = 40, 5e-3
+    diags = pdgen.bary_set(7, n_diag=4, lo=20, hi=80, template_size=60)
+    with pds.Context(d, g, tol=1e-4, max_iter=20000) as ctx:
+        H = torch.from_numpy(np.stack([ground.discretize(x, d) for x in diags]).astype(np.float32)).cuda()
+        z, _, _ = pds.pd_barycenter(ctx, H, lam=5.0, max_outer=3, energy_rtol=0.0)
+        assert float(pds.pd_quantize(ctx, z).sum().item()) == 0.0   # the smeared barycenter
+        pds.pd_sharpen(ctx, z, 2.0)
+        edge = np.zeros((d, d), np.float32)
+        edge[0, :6] = [0.49999997, 0.5, 1.5, 2.5000002, 1e-30, 3.0]
+        Z = torch.stack([z, torch.from_numpy(edge).cuda()]).contiguous()
+        q = pds.pd_quantize(ctx, Z).cpu().numpy()
+        pds.pd_quantize(ctx, Z, out=Z)
+        torch.cuda.synchronize()
+        zin = np.stack([z.cpu().numpy(), edge])
+        ref = sharpen.quantize(zin).astype(np.float32)
+        np.testing.assert_array_equal(q, ref)
+        np.testing.assert_array_equal(Z.cpu().numpy(), ref)
+        assert q[1, 0, :6].tolist() == [0.0, 1.0, 2.0, 3.0, 0.0, 3.0]
+        assert q[0].sum() > 0
