@@ -84,6 +84,11 @@ def test_strerror_and_host_side_validation():
     e, o = ctypes.c_double(), ctypes.c_int32()
     assert lib.pd_barycenter(None, 1, None, 5.0, 10, 0.01, 1, None, ctypes.byref(e), ctypes.byref(o), None, 0,
                              None) == _lib.PDSINK_EINVAL
+    assert lib.pd_sharpen(None, 1, None, 1.0, None, None) == _lib.PDSINK_EINVAL
+    assert lib.pd_quantize(None, 1, None, None, None) == _lib.PDSINK_EINVAL
+    assert lib.kmeans_lloyd(None, 1, None, 1, None, 1, 5.0, 10, 0.01, None, None, None, None, 0,
+                            None) == _lib.PDSINK_EINVAL
+    assert lib.pdsink_strerror(_lib.PDSINK_ERANGE) != lib.pdsink_strerror(_lib.PDSINK_EINVAL)
 
 
 def test_product_package_does_not_import_the_oracle():

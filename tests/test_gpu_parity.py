@@ -751,6 +751,10 @@ def test_sharpen_matches_oracle(pds, d):
             else:
                 assert abs(b - rb) <= 1e-12 * rb, (q, b, rb)
             np.testing.assert_allclose(Z.cpu().numpy(), ref, rtol=2e-6, atol=1e-30)   # float32 denormals
+        # targets that are not a finite entropy are refused before any launch
+        for bad in (-1.0, float("nan"), float("inf")):
+            with pytest.raises(pds.PdsinkError):
+                pds.pd_sharpen(ctx, torch.from_numpy(zs[0].copy()).cuda(), bad)
         # a batch of three with one target
         Zb = torch.from_numpy(np.stack([zs[0], zs[3], zs[6]])).cuda().contiguous()
         beta = pds.pd_sharpen(ctx, Zb, 1.5).cpu().numpy()
