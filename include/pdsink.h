@@ -170,6 +170,42 @@ int sinkhorn_dist_batch(pdsink_ctx* ctx, int64_t n_pairs,
                         double* cost, int32_t* iters, float* err, int32_t* status,
                         void* ws, size_t ws_bytes, void* stream);
 
+/* Completion record of one pair (sinkhorn_dist_batch_notify): the pair's
+ * outputs, then `tag`, which the device stores last with release ordering at
+ * system scope.  A host thread that reads tag equal to the call's tag, and
+ * only then the other fields, sees the pair's final outputs.  32 bytes. */
+typedef struct {
+  double   cost;
+  float    err;
+  int32_t  status;
+  int32_t  iters[2];
+  uint32_t tag;
+  uint32_t reserved;    /* not written */
+} pdsink_done;
+
+/* sinkhorn_dist_batch (state NULL; same iteration, outputs and workspace,
+ * Algorithm 1 of section 3) that also posts each pair's outputs to done[q] as
+ * soon as they are final, while the launches of the call still run: for a
+ * serving loop that completes a request when its own pairs are done, not when
+ * the whole batch is.  A pair's outputs are final at the end of its solve,
+ * or, when that solve flags it NONFINITE or RANGE, after the log-domain
+ * re-solve (the last launch of the call posts those pairs).  Every pair is
+ * posted exactly once per call, before the call's work on `stream` is done.
+ *   done  pdsink_done [n_pairs] out: host memory the device can write
+ *         (hipHostMalloc, e.g. pinned torch tensors) or device memory;
+ *         records are written whole, tag last; `reserved` is not written
+ *   tag   non-zero value written to done[q].tag; use a new tag per call on
+ *         reused records, so that a record of an earlier call is not taken
+ *         for this one
+ * PDSINK_EINVAL when done is NULL or tag is 0 (n_pairs > 0); otherwise as
+ * sinkhorn_dist_batch. */
+int sinkhorn_dist_batch_notify(pdsink_ctx* ctx, int64_t n_pairs,
+                               const float* hist_a, const float* hist_b,
+                               const int32_t* ia, const int32_t* ib,
+                               double* cost, int32_t* iters, float* err, int32_t* status,
+                               pdsink_done* done, uint32_t tag,
+                               void* ws, size_t ws_bytes, void* stream);
+
 /* sinkhorn_dist_batch with no workspace argument and no device allocation, for
  * callers that cannot allocate (code under HIP graph capture, tight serving
  * loops, harnesses that forbid hipMalloc).  The routing flags, launch order

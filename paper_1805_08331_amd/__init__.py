@@ -21,7 +21,8 @@ import torch
 from . import _lib
 from ._lib import PdsinkError  # noqa: F401
 
-__all__ = ["Context", "pd_discretize", "sinkhorn_dist_batch", "sinkhorn_dist_batch_noalloc", "pd_barycenter",
+__all__ = ["Context", "pd_discretize", "sinkhorn_dist_batch", "sinkhorn_dist_batch_noalloc",
+           "sinkhorn_dist_batch_notify", "done_records", "done_view", "pd_barycenter",
            "kmeans_assign", "pd_sharpen", "pd_quantize", "PdsinkError", "FP32", "BF16_REFINE"]
 
 FP32 = _lib.PDSINK_FP32
@@ -199,6 +200,41 @@ def sinkhorn_dist_batch(ctx: Context, hist_a: torch.Tensor, hist_b: torch.Tensor
     _lib.check("sinkhorn_dist_batch", _lib.load().sinkhorn_dist_batch(
         ctx.handle, n, _vp(hist_a), _vp(hist_b), _vp(ia), _vp(ib), _vp(state), _vp(out.cost), _vp(out.iters),
         _vp(out.err), _vp(out.status), _vp(ws), ws.numel(), _stream()))
+    return out
+
+
+def done_records(n: int) -> torch.Tensor:
+    """Pinned host memory for ``n`` completion records (``pdsink_done``), all
+    tags zero; view it with ``done_view``."""
+    return torch.zeros(n * _lib.DONE_DTYPE.itemsize, dtype=torch.uint8, pin_memory=True)
+
+
+def done_view(done: torch.Tensor) -> np.ndarray:
+    """The records of ``done`` (from ``done_records``) as a numpy structured
+    array over the same host memory (fields cost, err, status, iters, tag)."""
+    return done.numpy().view(_lib.DONE_DTYPE)
+
+
+def sinkhorn_dist_batch_notify(ctx: Context, hist_a: torch.Tensor, hist_b: torch.Tensor, ia: torch.Tensor,
+                               ib: torch.Tensor, done: torch.Tensor, tag: int, out: DistResult | None = None,
+                               ws: torch.Tensor | None = None, check_indices: bool = True) -> DistResult:
+    """``sinkhorn_dist_batch`` that posts each pair's outputs to the pinned
+    records ``done`` (``done_records(n)``) as soon as they are final, with
+    ``tag`` (non-zero, new per call on reused records) stored last."""
+    n, out = _pair_args(ctx, hist_a, hist_b, ia, ib, out, check_indices)
+    if not isinstance(done, torch.Tensor) or done.device.type != "cpu" or done.dtype != torch.uint8 \
+            or not done.is_contiguous() or not done.is_pinned():
+        raise ValueError("done must be pinned contiguous uint8 host memory (done_records)")
+    if done.numel() < n * _lib.DONE_DTYPE.itemsize:
+        raise ValueError("done holds fewer records than pairs")
+    if not 0 < int(tag) < 1 << 32:
+        raise ValueError("tag must be a non-zero uint32")
+    if ws is None:
+        ws = ctx.workspace(_lib.PDSINK_OP_DIST, n)
+    _lib.check("sinkhorn_dist_batch_notify", _lib.load().sinkhorn_dist_batch_notify(
+        ctx.handle, n, _vp(hist_a), _vp(hist_b), _vp(ia), _vp(ib), _vp(out.cost), _vp(out.iters),
+        _vp(out.err), _vp(out.status), ctypes.c_void_p(done.data_ptr()), int(tag), _vp(ws), ws.numel(),
+        _stream()))
     return out
 
 

@@ -8,6 +8,8 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 # PDSINK_PROFILE_BUILD=1 selects the instrumented build (phase cycle counters,
 # python -m paper_1805_08331_amd.build --profile); it computes the same results.
@@ -58,6 +60,11 @@ PDSINK_ST_LOG_PATH = 8
 PDSINK_NOALLOC_SCRATCH_BYTES = 64 << 20
 PDSINK_NOALLOC_MAX_PAIRS = 1 << 18
 
+# pdsink_done: one pair's completion record (tag stored last by the device)
+DONE_DTYPE = np.dtype([("cost", "<f8"), ("err", "<f4"), ("status", "<i4"), ("iters", "<i4", (2,)),
+                       ("tag", "<u4"), ("reserved", "<u4")])
+assert DONE_DTYPE.itemsize == 32
+
 PDSINK_OP_DIST = 0
 PDSINK_OP_KMEANS = 1
 PDSINK_OP_BARYCENTER = 2
@@ -74,6 +81,8 @@ SIGNATURES = {
     "sinkhorn_dist_batch": (c_int, [c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
                                     c_vp, c_size, c_vp]),
     "sinkhorn_dist_batch_noalloc": (c_int, [c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "sinkhorn_dist_batch_notify": (c_int, [c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
+                                           ctypes.c_uint32, c_vp, c_size, c_vp]),
     "sinkhorn_dist_bounds_batch": (c_int, [c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
                                            c_vp, c_vp, c_vp, c_size, c_vp]),
     "pd_barycenter": (c_int, [c_vp, c_i64, c_vp, c_dbl, c_i32, c_dbl, c_i32, c_vp,

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <cstddef>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -239,7 +240,13 @@ struct PairExtras {
   double* upper = nullptr;    // [n_pairs] error-control bounds
   double* lower = nullptr;
   char* order = nullptr;      // order_bytes(n_pairs): keys, permutation, buckets
+  DoneRec* done = nullptr;    // per-pair completion records, posted with done_tag
+  unsigned done_tag = 0;
 };
+
+static_assert(sizeof(pdsink_done) == sizeof(DoneRec) && offsetof(pdsink_done, tag) == offsetof(DoneRec, tag) &&
+                  offsetof(pdsink_done, iters) == offsetof(DoneRec, it),
+              "pdsink_done and DoneRec share one layout");
 
 size_t list_bytes(int D) { return align256((size_t)52 * D * D); }   // 2 sides x 5 arrays + 3 suspect arrays, x D^2 x 4 bytes
 size_t warm_bytes(int D) {
@@ -295,6 +302,22 @@ int launch_levels(PairParams pp, int n_slots, bool resident, hipStream_t st) {
   return last_error();
 }
 
+int launch_log(const pdsink_ctx* ctx, int64_t n_pairs, const float* ha, const float* hb, const int32_t* ia,
+               const int32_t* ib, double* cost, int32_t* iters, float* err, int32_t* status, const PairExtras& ex,
+               hipStream_t st);
+
+// Completion records of the pairs whose status carries NONFINITE, RANGE or
+// LOG_PATH: the solve launches post every other pair themselves.
+__global__ void done_sweep_kernel(long long n, const double* __restrict__ cost, const int32_t* __restrict__ iters,
+                                  const float* __restrict__ err, const int32_t* __restrict__ status, DoneRec* done,
+                                  unsigned tag) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const int st = status[q];
+  if (st & (PDSINK_ST_NONFINITE | PDSINK_ST_RANGE | PDSINK_ST_LOG_PATH))
+    post_done(done, tag, q, cost[q], iters[2 * q], iters[2 * q + 1], err[q], st);
+}
+
 int run_pairs(const pdsink_ctx* ctx, int64_t n_pairs, const float* ha, const float* hb, const int32_t* ia,
               const int32_t* ib, double* cost, int32_t* iters, float* err, int32_t* status, unsigned char* redo,
               const PairExtras& ex, hipStream_t st) {
@@ -328,6 +351,8 @@ int run_pairs(const pdsink_ctx* ctx, int64_t n_pairs, const float* ha, const flo
   pp.state_in = ex.state_in;
   pp.gout = ex.gout;
   pp.stop = ex.stop;
+  pp.done = ex.done;
+  pp.done_tag = ex.done_tag;
   pp.upper = ex.upper;
   pp.lower = ex.lower;
   pp.gamma = ctx->prm.gamma;
@@ -357,7 +382,23 @@ int run_pairs(const pdsink_ctx* ctx, int64_t n_pairs, const float* ha, const flo
     case 128: rc = launch_levels<128>(pp, ex.n_slots, resident, st); break;
     default: rc = launch_levels<256>(pp, ex.n_slots, resident, st); break;
   }
-  if (rc || ex.state || ex.gout) return rc;
+  if (rc) return rc;
+  if (!ex.state && !ex.gout) {
+    rc = launch_log(ctx, n_pairs, ha, hb, ia, ib, cost, iters, err, status, ex, st);
+    if (rc) return rc;
+  }
+  if (!ex.done) return PDSINK_OK;
+  // Completion records of the pairs the solve launches did not post (flagged
+  // NONFINITE or RANGE there): their results are final once the log-domain
+  // launches are done.
+  hipLaunchKernelGGL(done_sweep_kernel, dim3((unsigned)((n_pairs + WG - 1) / WG)), dim3(WG), 0, st,
+                     (long long)n_pairs, cost, iters, err, status, ex.done, ex.done_tag);
+  return last_error();
+}
+
+int launch_log(const pdsink_ctx* ctx, int64_t n_pairs, const float* ha, const float* hb, const int32_t* ia,
+               const int32_t* ib, double* cost, int32_t* iters, float* err, int32_t* status, const PairExtras& ex,
+               hipStream_t st) {
   // Pairs flagged NONFINITE or RANGE are solved again in the log domain (same
   // stream, no host synchronisation; a launch that only reads the flags when
   // none is).  Not for the barycenter solves, which need the scaled form of v.
@@ -749,7 +790,8 @@ __global__ void quantize_kernel(const float* __restrict__ z, int64_t total, floa
 // scaled warm-start records.
 int dist_impl(pdsink_ctx* ctx, int64_t n_pairs, const float* hist_a, const float* hist_b, const int32_t* ia,
               const int32_t* ib, double* state, double* cost, int32_t* iters, float* err, int32_t* status,
-              double* upper, double* lower, void* ws, size_t ws_bytes, void* stream) {
+              double* upper, double* lower, void* ws, size_t ws_bytes, void* stream, pdsink_done* done = nullptr,
+              uint32_t done_tag = 0) {
   if (!ctx || n_pairs < 0) return PDSINK_EINVAL;
   if (n_pairs == 0) return PDSINK_OK;
   if (n_pairs > INT_MAX || !hist_a || !hist_b || !ia || !ib || !cost || !iters || !err || !status)
@@ -767,6 +809,8 @@ int dist_impl(pdsink_ctx* ctx, int64_t n_pairs, const float* hist_a, const float
   ex.order = ex.lists + ex.n_slots * slot_bytes(ctx->D);
   ex.upper = upper;
   ex.lower = lower;
+  ex.done = reinterpret_cast<DoneRec*>(done);
+  ex.done_tag = done_tag;
   if (state) {
     ex.state = ex.order + order_bytes(n_pairs);
     ex.state_in = 1;
@@ -930,6 +974,15 @@ int sinkhorn_dist_batch(pdsink_ctx* ctx, int64_t n_pairs, const float* hist_a, c
                         float* err, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
   return dist_impl(ctx, n_pairs, hist_a, hist_b, ia, ib, state, cost, iters, err, status, nullptr, nullptr, ws,
                    ws_bytes, stream);
+}
+
+int sinkhorn_dist_batch_notify(pdsink_ctx* ctx, int64_t n_pairs, const float* hist_a, const float* hist_b,
+                               const int32_t* ia, const int32_t* ib, double* cost, int32_t* iters, float* err,
+                               int32_t* status, pdsink_done* done, uint32_t tag, void* ws, size_t ws_bytes,
+                               void* stream) {
+  if (n_pairs > 0 && (!done || tag == 0)) return PDSINK_EINVAL;
+  return dist_impl(ctx, n_pairs, hist_a, hist_b, ia, ib, nullptr, cost, iters, err, status, nullptr, nullptr, ws,
+                   ws_bytes, stream, done, tag);
 }
 
 int sinkhorn_dist_batch_noalloc(pdsink_ctx* ctx, int64_t n_pairs, const float* hist_a, const float* hist_b,

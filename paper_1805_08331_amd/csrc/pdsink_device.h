@@ -27,6 +27,32 @@ __device__ __forceinline__ double ldxd(double x, int e) {
 // floor(log2 x) for finite x > 0 (exact: the exponent field).
 __device__ __forceinline__ int ilog2f(float x) { return __builtin_amdgcn_frexp_expf(x) - 1; }
 
+// Completion record of one pair, for callers that pick up each result while
+// the launch that computes it still runs (same layout as pdsink_done in the
+// C header): the outputs first, then the tag, stored with release ordering
+// at system scope, so that a host thread which reads the tag and then the
+// other fields sees their final values.
+struct DoneRec {
+  double cost;
+  float err;
+  int status;
+  int it[2];
+  unsigned tag;
+  unsigned reserved;
+};
+static_assert(sizeof(DoneRec) == 32, "pdsink_done layout");
+
+__device__ __forceinline__ void post_done(DoneRec* done, unsigned tag, long long q, double cost, int it_lp, int it_hp,
+                                          float err, int st) {
+  DoneRec* r = done + q;
+  r->cost = cost;
+  r->err = err;
+  r->status = st;
+  r->it[0] = it_lp;
+  r->it[1] = it_hp;
+  __hip_atomic_store(&r->tag, tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Wait for the last MFMA of a K-loop to retire before its accumulators are
 // read.  Measured on gfx950: with only the compiler-inserted wait states, the
 // ds_write of the last accumulator register of v_mfma_f32_32x32x2_f32 read a

@@ -1032,6 +1032,7 @@ __device__ __forceinline__ void fast_solve_pair(const PairParams& prm, FastSmem&
       prm.iters[2 * pair + 1] = 0;
       prm.err[pair] = 0.0f;
       prm.status[pair] = 0;
+      if (prm.done) post_done(prm.done, prm.done_tag, pair, 0.0, 0, 0, 0.0f, 0);
     }
     return;
   }
@@ -1296,6 +1297,7 @@ __device__ __forceinline__ void fast_solve_pair(const PairParams& prm, FastSmem&
     prm.iters[2 * pair + 1] = it_hp;
     prm.err[pair] = (float)err;
     prm.status[pair] = st;
+    if (prm.done && !(st & 6)) post_done(prm.done, prm.done_tag, pair, cost, it_lp, it_hp, (float)err, st);
   }
   pf.mark(PH_COST);
   pf.count(PH_N_PAIRS);

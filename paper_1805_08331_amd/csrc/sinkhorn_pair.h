@@ -94,6 +94,11 @@ struct PairParams {
   // optional device flag: when it is set the launch does nothing (the
   // barycenter's outer steps after its stopping test)
   const int* stop;
+  // optional per-pair completion records (host-mapped or device memory): a
+  // pair whose result is final here (no NONFINITE or RANGE flag, which the
+  // log-domain launch takes up) posts it with done_tag
+  DoneRec* done;
+  unsigned done_tag;
   // optional error-control bounds of section 3 per pair (upper: rounded plan,
   // lower: c-transform dual), with the ground exponent and gamma they need
   double* upper;
@@ -795,6 +800,37 @@ __device__ __forceinline__ void gemm_kt(PairSmem<D>& s, const int* P, float* Wb,
 // up to 16: X is zero beyond its d columns and the kernels beyond d rows, and
 // nothing reads T or W beyond the tiles of the grid (d = 200: 49 of 64 tiles
 // at depth 208 of 256).
+// One accumulation chain of nst BF16 MFMA steps over operands in the
+// workspace slice (L2-resident): the loads run PFG steps ahead in a rotating
+// register buffer, so that several global reads are in flight behind each
+// MFMA; the scheduling barriers keep that order.
+template <int PFG>
+__device__ __forceinline__ void chain_bf16_g(const __bf16* pa, const __bf16* pb, int nst, floatx16& acc) {
+  bf16x8 a[PFG], b[PFG];
+#pragma unroll
+  for (int u = 0; u < PFG; ++u) {
+    if (u < nst) {
+      a[u] = *reinterpret_cast<const bf16x8*>(pa + 16 * u);
+      b[u] = *reinterpret_cast<const bf16x8*>(pb + 16 * u);
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  for (int st0 = 0; st0 < nst; st0 += PFG) {
+#pragma unroll
+    for (int u = 0; u < PFG; ++u) {
+      const int st = st0 + u;
+      if (st < nst) {
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[u], b[u], acc, 0, 0, 0);
+        if (st + PFG < nst) {
+          a[u] = *reinterpret_cast<const bf16x8*>(pa + 16 * (st + PFG));
+          b[u] = *reinterpret_cast<const bf16x8*>(pb + 16 * (st + PFG));
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
 template <int D, bool BF16, bool WEIGHTED>
 __device__ __forceinline__ void gemm_xk_g(PairSmem<D>& s, const int* Q, bool trim, int d) {
   constexpr int LDF = Cfg<D>::LDF, LDB = Cfg<D>::LDB;
@@ -809,16 +845,15 @@ __device__ __forceinline__ void gemm_xk_g(PairSmem<D>& s, const int* Q, bool tri
     if constexpr (BF16) {
       const __bf16* xa = opXb<D>(s) + row * LDB + 8 * lk;
       const __bf16* kb = opK2b<D>(s) + j * LDB + 8 * lk;
-#pragma unroll 2
-      for (int l0 = lbeg; l0 < KD; l0 += 16) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(xa + l0);
-        const bf16x8 b = *reinterpret_cast<const bf16x8*>(kb + l0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-      }
+      chain_bf16_g<4>(xa + lbeg, kb + lbeg, (KD - lbeg) >> 4, acc);
       mfma_drain();
-      __bf16* tt = opTtb<D>(s);
+      // four 8-byte stores per lane (columns tk * 32 + 8 q + 4 lk .. + 3 of row j)
+      typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+      __bf16* tt = opTtb<D>(s) + j * LDB + tk * 32 + 4 * lk;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) tt[j * LDB + tk * 32 + 8 * (r >> 2) + 4 * lk + (r & 3)] = (__bf16)acc[r];
+      for (int q = 0; q < 4; ++q)
+        *reinterpret_cast<bf16x4*>(tt + 8 * q) =
+            bf16x4{(__bf16)acc[4 * q], (__bf16)acc[4 * q + 1], (__bf16)acc[4 * q + 2], (__bf16)acc[4 * q + 3]};
     } else {
       const int Sj = s.S[j];
       const float* X = opXf<D>(s);
@@ -849,12 +884,7 @@ __device__ __forceinline__ void gemm_kt_g(PairSmem<D>& s, const int* P, float* W
     if constexpr (BF16) {
       const __bf16* ka = opK1b<D>(s) + i * LDB + 8 * lk;
       const __bf16* tb = opTtb<D>(s) + j * LDB + 8 * lk;
-#pragma unroll 2
-      for (int k0 = 0; k0 < KD; k0 += 16) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(ka + k0);
-        const bf16x8 b = *reinterpret_cast<const bf16x8*>(tb + k0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-      }
+      chain_bf16_g<4>(ka, tb, KD >> 4, acc);
     } else {
       const int Ri = s.R[i];
       const float* T = opTf<D>(s);
@@ -1887,6 +1917,7 @@ __device__ __forceinline__ void solve_pair(const PairParams& prm, PairSmem<D>& s
       prm.iters[2 * pair + 1] = 0;
       prm.err[pair] = 0.0f;
       prm.status[pair] = 0;
+      if (prm.done) post_done(prm.done, prm.done_tag, pair, 0.0, 0, 0, 0.0f, 0);
       if constexpr (BOUNDS) {
         if (prm.upper) prm.upper[pair] = 0.0;
         if (prm.lower) prm.lower[pair] = 0.0;
@@ -2121,6 +2152,7 @@ __device__ __forceinline__ void solve_pair(const PairParams& prm, PairSmem<D>& s
     prm.iters[2 * pair + 1] = it_hp;
     prm.err[pair] = (float)err;
     prm.status[pair] = st;
+    if (prm.done && !(st & 6)) post_done(prm.done, prm.done_tag, pair, cost, it_lp, it_hp, (float)err, st);
   }
 }
 

@@ -6,24 +6,29 @@ device (the assignment step of k-means, k pairs).  Requests come at any of
 several grid sizes d.  The loop keeps, per grid, one ``Context``, the
 resident centroid histograms; all grids share a fixed pool of launch slots,
 a slot being a HIP stream (default priority) with at most one launch in
-flight.  The pool should be no larger than the hardware queues the process
+flight.  A launch is one call of ``sinkhorn_dist_batch_notify`` over every
+pair of its requests (a distance is one pair, an assignment k pairs against
+the grid's centroids), which posts each pair's result to pinned host memory
+as soon as that pair is solved: a request completes when its own pairs are
+done, not when the slowest pair of its launch is.  The pool should be no larger than the hardware queues the process
 gets (``GPU_MAX_HW_QUEUES``, read when the HIP runtime starts; four by
 default): streams beyond that share a queue, and a short launch then waits
 behind a long one on the same queue.  More queues let more launches overlap:
-a launch retires only when its slowest pair is done, and while it waits the
-other slots keep the chip busy.  Each turn of
-``Server.poll``:
+a slot is free again once its launch has ended, and while it runs the
+other slots keep the chip busy.  Each turn of ``Server.poll``:
 
-1. retires finished launches: a HIP event per launch is queried without
-   blocking; the launch's outputs were already copied to pinned host memory
-   on its own stream, so its requests get their results and completion time;
+1. collects results: for every launch in flight, the completion records its
+   pairs have posted so far (the tag of a record is stored last, so a tagged
+   record is whole); a request whose pairs are all posted gets its results
+   and completion time.  A launch whose HIP event has passed (queried without
+   blocking) has posted every pair; its slot and memory are released;
 2. gives each free slot to the grid whose oldest waiting request is the
    oldest, and admits that grid's waiting requests, oldest first, a request
    whole (its one pair, or its k pairs), up to a pair cap per launch
    and within a device-memory budget counted over all launches in flight;
 3. launches the batch on the slot's stream: discretisation of the batch's
-   diagrams, the distance batch and the assignment batch, then the copies
-   back.  Launches in different slots and at different grids run on the
+   diagrams, a copy of the grid's centroids behind them (assignments), and
+   one distance call over all pairs.  Launches in different slots and at different grids run on the
    device at the same time; requests that arrive meanwhile wait for the next
    free slot.
 
@@ -46,7 +51,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import torch
 
-from . import Context, _lib, autotune, kmeans_assign, pd_discretize, sinkhorn_dist_batch
+from . import Context, _lib, autotune, done_records, done_view, pd_discretize, sinkhorn_dist_batch_notify
 
 DIST = 0
 ASSIGN = 1
@@ -61,7 +66,7 @@ class Request:
     diagrams: list
     t_arrival: float = 0.0
     rid: int = -1
-    # results, filled when the launch that served the request has finished
+    # results, filled when the request's pairs have posted theirs
     cost: float | None = None          # DIST: Sinkhorn cost
     assign: int | None = None          # ASSIGN: nearest centroid
     dists: np.ndarray | None = None    # ASSIGN: costs to the k centroids
@@ -96,6 +101,27 @@ def plan_batch(waiting, k: int, max_pairs: int, budget: int, req_bytes, ws_bytes
     return batch
 
 
+def nearest_centroid(dists) -> int:
+    """Index of the smallest cost, as the library's assignment step takes it:
+    ties keep the lowest index and NaN never wins (0 when none is finite)."""
+    v = np.asarray(dists, np.float64)
+    v = np.where(np.isnan(v), np.inf, v)
+    return int(np.argmin(v))
+
+
+def completed(tags, tag: int, starts, open_mask) -> np.ndarray:
+    """Requests that are complete: request i owns records [starts[i],
+    starts[i + 1]) (``starts`` has one entry more than requests) and is
+    complete when each of them carries ``tag``.  Returns the indices of the
+    complete requests among those still open (``open_mask``)."""
+    posted = np.asarray(tags) == tag
+    starts = np.asarray(starts)
+    # number of untagged records per request, by a prefix sum over records
+    missing = np.concatenate(([0], np.cumsum(~posted)))
+    done = (missing[starts[1:]] - missing[starts[:-1]]) == 0
+    return np.nonzero(done & open_mask)[0]
+
+
 def latency_summary(latencies) -> dict:
     """p50 / p99 / max of a list of latencies in seconds, in milliseconds
     (nearest-rank percentiles)."""
@@ -113,8 +139,11 @@ def latency_summary(latencies) -> dict:
 class _Launch:
     reqs: list
     event: torch.cuda.Event
-    host: dict
-    keep: list            # device tensors that must outlive the launch
+    done: torch.Tensor    # pinned completion records, one per pair
+    tag: int
+    starts: np.ndarray    # request i owns pairs [starts[i], starts[i + 1])
+    open: np.ndarray      # requests without results yet
+    keep: list            # tensors that must outlive the launch
     nbytes: int
 
 
@@ -176,6 +205,7 @@ class Server:
         self.n_launches = 0
         self.done = []
         self._next_id = 0
+        self._tag = 0
 
     def close(self):
         for s in self.streams:
@@ -205,8 +235,14 @@ class Server:
 
     @property
     def pending(self) -> int:
+        """Requests without results: waiting, or in a launch that has not
+        posted all of their pairs yet."""
         return sum(len(g.waiting) for g in self.grids.values()) + sum(
-            len(b[1].reqs) for b in self.busy if b is not None)
+            int(b[1].open.sum()) for b in self.busy if b is not None)
+
+    @property
+    def launches_in_flight(self) -> int:
+        return sum(b is not None for b in self.busy)
 
     # -- memory accounting --------------------------------------------------
     def _req_bytes(self, g: _Grid, r: Request) -> int:
@@ -215,19 +251,21 @@ class Server:
         d = g.ctx.d
         nd = len(r.diagrams)
         b = nd * (d * d * 4 + 8 + 8) + sum(len(x) for x in r.diagrams) * 8
-        return b + (8 + 8 + 4 + 4 + 4 if r.kind == DIST else 4 + self.k * 12)
+        # per pair: indices, outputs (cost, iterations, error, status)
+        return b + r.n_pairs(self.k) * (4 + 4 + 8 + 8 + 4 + 4)
 
     def _ws_bytes(self, g: _Grid, n_dist: int, n_asg: int) -> int:
-        """Workspace bytes of a launch with ``n_dist`` distance and ``n_asg``
-        assignment requests (memoised per grid)."""
-        b = 0
-        for op, n in ((_lib.PDSINK_OP_DIST, n_dist), (_lib.PDSINK_OP_KMEANS, n_asg * self.k)):
-            if n:
-                key = (op, n)
-                if key not in g.ws_cache:
-                    g.ws_cache[key] = g.ctx.workspace_bytes(op, n)
-                b += g.ws_cache[key] + 64
-        return b
+        """Bytes of a launch with ``n_dist`` distance and ``n_asg`` assignment
+        requests beyond its requests' own: the workspace of its one distance
+        call (memoised per grid) and, with assignments, the copy of the grid's
+        centroids behind the batch's histograms."""
+        n = n_dist + n_asg * self.k
+        if n == 0:
+            return 0
+        if n not in g.ws_cache:
+            g.ws_cache[n] = g.ctx.workspace_bytes(_lib.PDSINK_OP_DIST, n)
+        cen = self.k * g.ctx.d * g.ctx.d * 4 if n_asg else 0
+        return g.ws_cache[n] + 64 + cen
 
     def _launch_bytes(self, g: _Grid, reqs) -> int:
         n_dist = sum(1 for r in reqs if r.kind == DIST)
@@ -270,63 +308,82 @@ class Server:
         """Poll until nothing waits or runs (raises TimeoutError after
         ``timeout_s``)."""
         t0 = time.perf_counter()
-        while self.pending:
+        while self.pending or self.launches_in_flight:
             if self.poll() == 0:
                 time.sleep(2e-5)
             if time.perf_counter() - t0 > timeout_s:
                 raise TimeoutError(f"{self.pending} requests still pending")
 
     def _retire(self) -> int:
+        """Results of the requests whose pairs have all posted; release of the
+        launches that have ended."""
         n = 0
         for s, b in enumerate(self.busy):
-            if b is None or not b[1].event.query():
+            if b is None:
                 continue
             L = b[1]
-            now = self.clock()
-            h = L.host
-            di = ai = 0
-            for r in L.reqs:
-                if r.kind == DIST:
-                    r.cost = float(h["cost"][di])
-                    r.status = h["dstatus"][di:di + 1].copy()
-                    di += 1
-                else:
-                    r.assign = int(h["assign"][ai])
-                    r.dists = h["adist"][ai].copy()
-                    r.status = h["astatus"][ai].copy()
-                    ai += 1
-                r.t_done = now
-                self.done.append(r)
-            n += len(L.reqs)
-            self.in_flight_bytes -= L.nbytes
-            self.busy[s] = None
+            # query the event before reading the records: once it has passed,
+            # every record of the launch is posted and visible
+            ended = L.event.query()
+            rec = done_view(L.done)
+            fin = completed(rec["tag"], L.tag, L.starts, L.open)
+            if ended and len(fin) != int(L.open.sum()):
+                raise RuntimeError(f"launch ended with {int(L.open.sum()) - len(fin)} requests unposted")
+            if len(fin):
+                now = self.clock()
+                for i in fin:
+                    r, lo, hi = L.reqs[i], L.starts[i], L.starts[i + 1]
+                    part = rec[lo:hi]
+                    if r.kind == DIST:
+                        r.cost = float(part["cost"][0])
+                    else:
+                        r.dists = part["cost"].copy()
+                        r.assign = nearest_centroid(r.dists)
+                    r.status = part["status"].copy()
+                    r.t_done = now
+                    self.done.append(r)
+                L.open[fin] = False
+                n += len(fin)
+            if ended:
+                self.in_flight_bytes -= L.nbytes
+                self.busy[s] = None
         return n
 
     def _launch(self, g: _Grid, stream, reqs) -> _Launch:
-        ctx, dev = g.ctx, g.ctx.device
-        dreq = [r for r in reqs if r.kind == DIST]
-        areq = [r for r in reqs if r.kind == ASSIGN]
-        keep, host = [], {}
+        ctx, dev, k = g.ctx, g.ctx.device, self.k
+        keep = []
         nbytes = self._launch_bytes(g, reqs)
+        # histograms of the batch's diagrams, in request order, then (with
+        # assignments) the centroids; pairs in request order
+        n_up = sum(len(r.diagrams) for r in reqs)
+        any_asg = any(r.kind == ASSIGN for r in reqs)
+        ia, ib, starts, row = [], [], [0], 0
+        for r in reqs:
+            if r.kind == DIST:
+                ia.append(row)
+                ib.append(row + 1)
+                row += 2
+            else:
+                ia += [row] * k
+                ib += range(n_up, n_up + k)
+                row += 1
+            starts.append(len(ia))
+        n = len(ia)
+        self._tag = self._tag % 0xFFFFFFFF + 1
+        done = done_records(n)
         with torch.cuda.stream(stream):
-            if dreq:
-                hist = _upload(ctx, [x for r in dreq for x in r.diagrams], keep)
-                ia = torch.arange(0, 2 * len(dreq), 2, dtype=torch.int32, device=dev)
-                ib = ia + 1
-                res = sinkhorn_dist_batch(ctx, hist, hist, ia, ib, check_indices=False)
-                keep += [hist, ia, ib, res]
-                host["cost"] = _to_host(res.cost)
-                host["dstatus"] = _to_host(res.status)
-            if areq:
-                hist = _upload(ctx, [r.diagrams[0] for r in areq], keep)
-                assign, dist, status = kmeans_assign(ctx, hist, g.centroids)
-                keep += [hist, assign, dist, status]
-                host["assign"] = _to_host(assign)
-                host["adist"] = _to_host(dist)
-                host["astatus"] = _to_host(status)
+            buf = torch.empty((n_up + (k if any_asg else 0), ctx.d, ctx.d), dtype=torch.float32, device=dev)
+            _upload(ctx, [x for r in reqs for x in r.diagrams], keep, out=buf)
+            if any_asg:
+                buf[n_up:].copy_(g.centroids)
+            hidx = torch.tensor([ia, ib], dtype=torch.int32).pin_memory()
+            didx = hidx.to(dev, non_blocking=True)
+            res = sinkhorn_dist_batch_notify(ctx, buf, buf, didx[0], didx[1], done, self._tag,
+                                             check_indices=False)
+            keep += [buf, hidx, didx, res]
             ev = torch.cuda.Event()
             ev.record(stream)
-        return _Launch(reqs, ev, {k: v.numpy() for k, v in host.items()}, keep, nbytes)
+        return _Launch(reqs, ev, done, self._tag, np.asarray(starts), np.ones(len(reqs), bool), keep, nbytes)
 
 
 def _checked_points(x) -> np.ndarray:
@@ -344,9 +401,9 @@ def _checked_points(x) -> np.ndarray:
     return a
 
 
-def _upload(ctx: Context, diagrams, keep) -> torch.Tensor:
+def _upload(ctx: Context, diagrams, keep, out=None) -> torch.Tensor:
     """Histograms of ``diagrams`` on the current stream (CSR points copied from
-    pinned host memory)."""
+    pinned host memory), into the first rows of ``out`` when given."""
     counts = np.array([len(x) for x in diagrams], np.int64)
     off = np.zeros(len(diagrams) + 1, np.int64)
     np.cumsum(counts, out=off[1:])
@@ -357,15 +414,9 @@ def _upload(ctx: Context, diagrams, keep) -> torch.Tensor:
     dp = hp.to(ctx.device, non_blocking=True)
     do = ho.to(ctx.device, non_blocking=True)
     keep += [hp, ho, dp, do]
-    hist, mass, n_bad = pd_discretize(ctx, dp, do)
+    hist, mass, n_bad = pd_discretize(ctx, dp, do, hist=out)
     keep += [mass, n_bad]
     return hist
-
-
-def _to_host(t: torch.Tensor) -> torch.Tensor:
-    h = torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
-    h.copy_(t, non_blocking=True)
-    return h
 
 
 def run_stream(server: Server, stream, realtime: bool = True, timeout_s: float = 120.0):
@@ -374,11 +425,11 @@ def run_stream(server: Server, stream, realtime: bool = True, timeout_s: float =
     submitted once the clock passes its arrival time and its latency counts
     from that arrival time; otherwise all are submitted at once.  Returns the
     requests (with results) and the wall time from the first arrival to the
-    last completion."""
+    last completion.  Returns once every launch has ended as well."""
     reqs = [Request(s["kind"], s["d"], s["diagrams"]) for s in stream]
     t0 = server.clock()
     i = 0
-    while i < len(reqs) or server.pending:
+    while i < len(reqs) or server.pending or server.launches_in_flight:
         now = server.clock()
         while i < len(reqs) and (not realtime or stream[i]["t"] <= now - t0):
             server.submit(reqs[i], t_arrival=t0 + (stream[i]["t"] if realtime else 0.0))

@@ -77,6 +77,8 @@ def test_strerror_and_host_side_validation():
                                    None) == _lib.PDSINK_EINVAL
     assert lib.sinkhorn_dist_batch_noalloc(None, 1, None, None, None, None, None, None, None, None,
                                            None) == _lib.PDSINK_EINVAL
+    assert lib.sinkhorn_dist_batch_notify(None, 1, None, None, None, None, None, None, None, None, None, 1, None,
+                                          0, None) == _lib.PDSINK_EINVAL
     assert lib.sinkhorn_dist_bounds_batch(None, 1, None, None, None, None, None, None, None, None, None, None,
                                           None, 0, None) == _lib.PDSINK_EINVAL
     assert lib.pd_discretize(None, None, None, 1, None, None, None, None) == _lib.PDSINK_EINVAL

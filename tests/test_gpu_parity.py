@@ -790,3 +790,81 @@ def test_quantize_bit_exact(pds):
         np.testing.assert_array_equal(Z.cpu().numpy(), ref)
         assert q[1, 0, :6].tolist() == [0.0, 1.0, 2.0, 3.0, 0.0, 3.0]
         assert q[0].sum() > 0
+
+
+def _spread(rng, n):
+    b = rng.random(n)
+    t = b + (1.0 - b) * rng.random(n)
+    return np.stack([b, t], 1).astype(np.float32)
+
+
+@pytest.mark.parametrize("d,g,prec,max_iter", [(100, 1e-3, "bf16", 3000), (64, 5e-5, "fp32", 800),
+                                               (136, 2e-3, "fp32", 400)])
+def test_notify_posts_every_pair(pds, d, g, prec, max_iter):
+    """sinkhorn_dist_batch_notify posts every pair exactly once, with the
+    call's tag and the pair's outputs, and those outputs are bit-identical to
+    sinkhorn_dist_batch's (the same launches run).  The batch mixes pairs of
+    the first-level kernel (the resident one at d = 100), an empty pair, a
+    pair whose supports exceed 512 cells (second level) and, at gamma d^2 =
+    0.2, pairs solved again in the log domain (posted by the last launch).
+    A second call on the same records with a new tag overwrites every record."""
+    rng = np.random.default_rng(17)
+    D1s, D2s = pdgen.pairs_batch(3, 24, 20, 200)
+    empty = np.zeros((0, 2), np.float32)
+    D1s = list(D1s) + [empty, _spread(rng, 3000)]
+    D2s = list(D2s) + [empty, pdgen.gen(rng, 80)]
+    n = len(D1s)
+    dev = torch.device("cuda")
+    with pds.Context(d, g, tol=1e-4, max_iter=max_iter, precision=prec) as ctx:
+        pts, off = pdgen.to_csr(D1s + D2s)
+        hist, _, bad = pds.pd_discretize(ctx, torch.from_numpy(pts).to(dev), torch.from_numpy(off).to(dev))
+        ia = torch.arange(0, n, dtype=torch.int32, device=dev)
+        ib = ia + n
+        ref = pds.sinkhorn_dist_batch(ctx, hist, hist, ia, ib)
+        done = pds.done_records(n)
+        rec = pds.done_view(done)
+        for tag in (5, 6):
+            out = pds.sinkhorn_dist_batch_notify(ctx, hist, hist, ia, ib, done, tag)
+            torch.cuda.synchronize()
+            assert int(bad.item()) == 0
+            assert np.all(rec["tag"] == tag), rec["tag"]
+            cost, iters = out.cost.cpu().numpy(), out.iters.cpu().numpy()
+            err, st = out.err.cpu().numpy(), out.status.cpu().numpy()
+            assert np.array_equal(cost, ref.cost.cpu().numpy(), equal_nan=True)
+            assert np.array_equal(st, ref.status.cpu().numpy()) and np.array_equal(iters, ref.iters.cpu().numpy())
+            assert np.array_equal(rec["cost"], cost, equal_nan=True) and np.array_equal(rec["status"], st)
+            assert np.array_equal(rec["iters"], iters) and np.array_equal(rec["err"], err)
+    supp = (hist.cpu().numpy() > 0).reshape(2 * n, -1).sum(1)
+    assert supp[n - 1] > 512 and cost[n - 2] == 0.0 and st[n - 2] == 0, (supp[n - 1], cost[n - 2], st[n - 2])
+    logp = (st & pds._lib.PDSINK_ST_LOG_PATH) != 0
+    print(f"d={d}: statuses {np.unique(st, return_counts=True)}", flush=True)
+    if d == 64:
+        assert logp.any(), st
+
+
+def test_notify_posts_before_the_launch_ends(pds):
+    """Records of finished pairs reach the host while the call's launches still
+    run: polling the records of a 1024-pair FP32 batch (tens of ms) sees
+    tagged records before the stream's event has passed, and after it every
+    record is tagged."""
+    D1s, D2s = pdgen.pairs_batch(0, 1024)
+    d, n = 100, 1024
+    dev = torch.device("cuda")
+    with pds.Context(d, 1e-3, tol=1e-3, max_iter=2000, precision="fp32") as ctx:
+        pts, off = pdgen.to_csr(list(D1s) + list(D2s))
+        hist, _, _ = pds.pd_discretize(ctx, torch.from_numpy(pts).to(dev), torch.from_numpy(off).to(dev))
+        ia = torch.arange(0, n, dtype=torch.int32, device=dev)
+        ib = ia + n
+        ws = ctx.workspace(pds._lib.PDSINK_OP_DIST, n)
+        done = pds.done_records(n)
+        rec = pds.done_view(done)
+        torch.cuda.synchronize()
+        pds.sinkhorn_dist_batch_notify(ctx, hist, hist, ia, ib, done, 9, ws=ws, check_indices=False)
+        ev = torch.cuda.Event()
+        ev.record()
+        early = 0
+        while not ev.query():
+            early = max(early, int((rec["tag"] == 9).sum()))
+        torch.cuda.synchronize()
+    print(f"records seen before the launch ended: {early} of {n}", flush=True)
+    assert 0 < early and np.all(rec["tag"] == 9)

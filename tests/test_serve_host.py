@@ -2,7 +2,7 @@
 launch and the latency statistics."""
 import numpy as np
 
-from paper_1805_08331_amd.serve import ASSIGN, DIST, Request, latency_summary, plan_batch
+from paper_1805_08331_amd.serve import ASSIGN, DIST, Request, completed, latency_summary, nearest_centroid, plan_batch
 
 
 def _reqs(kinds):
@@ -149,3 +149,31 @@ def test_submit_rejects_request_beyond_memory_budget():
     else:
         raise AssertionError("oversized request accepted")
     assert len(srv.grids[100].waiting) == 1 and srv._next_id == 1
+
+
+def test_completed_requests_from_posted_records():
+    """Requests own runs of records (one pair for a distance, k for an
+    assignment); a request is complete when every record of its run carries
+    the launch's tag.  Records of an earlier launch (another tag) do not
+    count, and requests already handed out are not returned again."""
+    starts = np.array([0, 1, 4, 5, 8])          # D, A(3), D, A(3)
+    tags = np.array([7, 7, 7, 0, 7, 7, 7, 7], np.uint32)
+    open_ = np.ones(4, bool)
+    assert list(completed(tags, 7, starts, open_)) == [0, 2, 3]
+    open_[[0, 2, 3]] = False
+    assert list(completed(tags, 7, starts, open_)) == []
+    tags[3] = 6                                 # a stale record from a previous launch
+    assert list(completed(tags, 7, starts, open_)) == []
+    tags[3] = 7
+    assert list(completed(tags, 7, starts, open_)) == [1]
+    assert list(completed(np.zeros(0, np.uint32), 1, np.array([0]), np.zeros(0, bool))) == []
+
+
+def test_nearest_centroid_rule():
+    """The library's assignment rule: smallest cost, ties to the lowest index,
+    NaN never wins, 0 when no cost is finite."""
+    assert nearest_centroid([3.0, 1.0, 2.0]) == 1
+    assert nearest_centroid([2.0, 1.0, 1.0]) == 1
+    assert nearest_centroid([np.nan, 5.0, 4.0]) == 2
+    assert nearest_centroid([np.nan, np.nan]) == 0
+    assert nearest_centroid([np.inf, np.inf, 3.0]) == 2
