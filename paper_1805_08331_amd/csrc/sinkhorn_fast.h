@@ -358,7 +358,8 @@ __device__ __forceinline__ void f_c1_bf16(const __bf16* X, const __bf16* K2, __b
   // v_mfma_f32_32x32x16_bf16) cover them (the FP32 chains keep mfma_drain).
   // Unconditional stores: rows j >= d go to the slot's spare row d + 1, and
   // groups of columns k >= KD to the pad columns KD .. KD + 3 of the row;
-  // neither is ever read.
+  // neither is ever read.  (Selecting the address keeps the epilogue free
+  // of branches, which cost more here than the stores they would skip.)
   typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
   __bf16* trow = Tt + (j < d ? j : d + 1) * LDB;
 #pragma unroll
@@ -377,18 +378,19 @@ __device__ __forceinline__ void f_c1_bf16(const __bf16* X, const __bf16* K2, __b
 // rows is one aligned 16-byte store.  A group whose first row lies on or
 // above the diagonal is stored whole (rows past j land in the column's
 // padding); other groups, and columns j >= d, go to a dummy slot of the lane.
+// The address is selected per lane, with no branch: on gfx950 a branch
+// around each store (even one uniform over the wave) made this epilogue
+// cost more than the stores themselves.
 __device__ __forceinline__ void f_store_w(float* Wp, const floatx16& acc, int ti, int tj, int d) {
   const int lane = threadIdx.x & 63, lr = lane & 31, lk = lane >> 5;
   const int i0 = ti * 32 + 4 * lk, j = tj * 32 + lr;
   float4* grp = reinterpret_cast<float4*>(Wp + widx(i0, j));
   float4* dummy = reinterpret_cast<float4*>(Wp + wcol(d)) + lane;
-  const bool inside = ti < tj && tj * 32 + 31 < d;   // every group of the tile is stored
+  const int lim = j < d ? j - i0 : -1;   // group q (rows i0 + 8q ..) is stored when 8q <= lim
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const float4 v = {acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
-    float4* dst = grp + 2 * q;
-    if (!inside) dst = (j < d && i0 + 8 * q <= j) ? dst : dummy;
-    *dst = v;
+    *(8 * q <= lim ? grp + 2 * q : dummy) = v;
   }
 }
 
