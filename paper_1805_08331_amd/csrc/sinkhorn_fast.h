@@ -528,6 +528,9 @@ __device__ __forceinline__ void f_c2_fp32(const FastSmem& s, const float* T, flo
   if (w < 4) {
     // one kernel entry for both tiles; operands of step k0 + 2 read while step k0 runs
     float a = f_kentry<WEIGHTED>(s, ia, lk, P, Ra), b0 = T[lk * LTF + ja], b1 = T[lk * LTF + ja + 32];
+    // (bounded unrolling: fully unrolled at the small grids' depths these
+    // loops pushed the whole kernel into scratch spills, 50 to 110 VGPRs)
+#pragma unroll 2
     for (int k0 = 0; k0 < KD; k0 += 2) {
       const int kn = (k0 + 2 < KD ? k0 + 2 : 0) + lk;
       const float na = f_kentry<WEIGHTED>(s, ia, kn, P, Ra), nb0 = T[kn * LTF + ja], nb1 = T[kn * LTF + ja + 32];
@@ -544,6 +547,7 @@ __device__ __forceinline__ void f_c2_fp32(const FastSmem& s, const float* T, flo
     const int H2 = KD / 2;
     float a0 = f_kentry<WEIGHTED>(s, ia, lk, P, Ra), b0 = T[lk * LTF + ja];
     float a1 = f_kentry<WEIGHTED>(s, ia, lk + H2, P, Ra), b1 = T[(lk + H2) * LTF + ja];
+#pragma unroll 2
     for (int k0 = 0; k0 < H2; k0 += 2) {
       const int kn = (k0 + 2 < H2 ? k0 + 2 : 0) + lk;
       const float na0 = f_kentry<WEIGHTED>(s, ia, kn, P, Ra), nb0 = T[kn * LTF + ja];
