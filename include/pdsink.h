@@ -54,9 +54,10 @@ extern "C" {
  * half steps in LDS between refits of the scales.  Pairs with a warm-start
  * state, barycenter solves, bounds and pairs the resident kernel cannot hold
  * (supports beyond 512 cells or below the diagonal) always run in the general
- * kernel; a RESIDENT context below d = 65 pads the tables and those kernels to
- * 128. */
-#define PDSINK_KERNEL_AUTO      0  /* resident for 65 <= d <= 100, general otherwise */
+ * kernel, at its own padding (a context at d <= 64 holds the resident
+ * kernel's 128-padded tables beside the general kernel's). */
+#define PDSINK_KERNEL_AUTO      0  /* resident for 33 <= d <= 100 with BF16_REFINE and
+                                    * for 65 <= d <= 100 with FP32; general otherwise */
 #define PDSINK_KERNEL_RESIDENT  1  /* resident kernel; d in [33, 100], else PDSINK_EINVAL */
 #define PDSINK_KERNEL_GENERAL   2  /* general kernel at every d */
 

@@ -44,6 +44,18 @@ struct pdsink_ctx {
   float* c1;
   float* cd;
   int* kb;
+  // the same seven tables in the 128-padded layout the resident kernel reads
+  // (the tables above when D = 128; their own allocation at grids 33 to 64,
+  // whose general kernel keeps the 64-padded layout; NULL where the context
+  // never runs the resident kernel)
+  int* rge;
+  float* rgm;
+  int* rgde;
+  float* rgdm;
+  float* rc1;
+  float* rcd;
+  int* rkb;
+  char* rbase;        // the resident tables' own allocation, or NULL
   int n_cu;           // compute units of the device: workgroups of the global-list variant
   void* scratch;      // device address of `scratch` on this device, NULL if the lookup failed
 };
@@ -76,11 +88,17 @@ int pad_grid(int d) { return d <= 32 ? 32 : (d <= 64 ? 64 : (d <= 128 ? 128 : 25
 
 // Grids the resident-kernel variant takes (K depth 16 ceil(d / 16), 3 to 7
 // MFMA steps), and whether a context runs it: on request, or by default where
-// it measured faster than the general kernel.
+// it measured faster than the general kernel (1024 pairs of 50-500 points,
+// gamma 1e-3, tol 1e-3): with BF16 contractions at every grid it takes (1.6x
+// to 2x at d = 40 to 100), with FP32 contractions from d = 65 (at d = 40 to
+// 64 the general kernel's 64-padded layout was as fast or faster: 21 against
+// 26 ms per batch at d = 50).
 constexpr int RESIDENT_DMIN = 33;
-bool resident_for(int d, int kernel) {
-  if (d < RESIDENT_DMIN || d > FAST_DMAX) return false;
-  return kernel == PDSINK_KERNEL_RESIDENT || (kernel == PDSINK_KERNEL_AUTO && d >= RESIDENT_AUTO_DMIN);
+bool resident_grid(int d) { return d >= RESIDENT_DMIN && d <= FAST_DMAX; }
+bool resident_for(int d, int kernel, int precision) {
+  if (!resident_grid(d)) return false;
+  if (kernel == PDSINK_KERNEL_RESIDENT) return true;
+  return kernel == PDSINK_KERNEL_AUTO && (precision == PDSINK_BF16_REFINE || d >= RESIDENT_AUTO_DMIN);
 }
 
 struct DeviceGuard {
@@ -268,22 +286,27 @@ int64_t slots_for(const pdsink_ctx* ctx, int64_t n_pairs) { return n_pairs < ctx
 // workgroup per compute unit striding over the batch.  Both launches go to
 // the same stream, with no host synchronisation; when no pair is flagged the
 // second launch only reads the flags.
+//
+// `rp`, when given, is pp with the resident kernel's tables (the 128-padded
+// layout): grids up to 100 without warm start or gradient output then run
+// level 0 in the resident-kernel variant, and the pairs it does not take
+// (supports beyond 512 cells or below the diagonal, suspect-list overflow)
+// go to the global-list launch of the general kernel at its own padding D.
 template <int D>
-int launch_levels(PairParams pp, int n_slots, bool resident, hipStream_t st) {
+int launch_levels(PairParams pp, const PairParams* rp, int n_slots, hipStream_t st) {
   if (pp.upper || pp.lower) return launch_pair_bounds(D, pp, n_slots, st) ? PDSINK_EDEVICE : PDSINK_OK;
   pp.only_redo = 0;
-  if constexpr (D == 128) {
-    // Grids up to 100 without warm start or gradient output: the resident-kernel
-    // variant; pairs it does not take (supports beyond 512 cells or below the
-    // diagonal, suspect-list overflow) go to the global-list launch.
-    if (resident && !pp.state && !pp.gout) {
-      const unsigned g = (unsigned)pp.n_pairs;
-      switch ((pp.d + 15) / 16) {
-        case 3: hipLaunchKernelGGL(sinkhorn_fast_kernel<3>, dim3(g), dim3(PWGS), 0, st, pp); break;
-        case 4: hipLaunchKernelGGL(sinkhorn_fast_kernel<4>, dim3(g), dim3(PWGS), 0, st, pp); break;
-        case 5: hipLaunchKernelGGL(sinkhorn_fast_kernel<5>, dim3(g), dim3(PWGS), 0, st, pp); break;
-        case 6: hipLaunchKernelGGL(sinkhorn_fast_kernel<6>, dim3(g), dim3(PWGS), 0, st, pp); break;
-        default: hipLaunchKernelGGL(sinkhorn_fast_kernel<7>, dim3(g), dim3(PWGS), 0, st, pp); break;
+  if constexpr (D <= 128) {
+    if (rp && !pp.state && !pp.gout) {
+      PairParams r = *rp;
+      r.only_redo = 0;
+      const unsigned g = (unsigned)r.n_pairs;
+      switch ((r.d + 15) / 16) {
+        case 3: hipLaunchKernelGGL(sinkhorn_fast_kernel<3>, dim3(g), dim3(PWGS), 0, st, r); break;
+        case 4: hipLaunchKernelGGL(sinkhorn_fast_kernel<4>, dim3(g), dim3(PWGS), 0, st, r); break;
+        case 5: hipLaunchKernelGGL(sinkhorn_fast_kernel<5>, dim3(g), dim3(PWGS), 0, st, r); break;
+        case 6: hipLaunchKernelGGL(sinkhorn_fast_kernel<6>, dim3(g), dim3(PWGS), 0, st, r); break;
+        default: hipLaunchKernelGGL(sinkhorn_fast_kernel<7>, dim3(g), dim3(PWGS), 0, st, r); break;
       }
       int rc = last_error();
       if (rc) return rc;
@@ -375,12 +398,23 @@ int run_pairs(const pdsink_ctx* ctx, int64_t n_pairs, const float* ha, const flo
     pp.perm = perm;
   }
   int rc;
-  const bool resident = ctx->D == 128 && resident_for(ctx->prm.d, ctx->prm.kernel);
+  PairParams rpp = pp;
+  const PairParams* rp = nullptr;
+  if (ctx->rge && resident_for(ctx->prm.d, ctx->prm.kernel, ctx->prm.precision)) {
+    rpp.ge = ctx->rge;
+    rpp.gm = ctx->rgm;
+    rpp.gde = ctx->rgde;
+    rpp.gdm = ctx->rgdm;
+    rpp.c1 = ctx->rc1;
+    rpp.cd = ctx->rcd;
+    rpp.kb = ctx->rkb;
+    rp = &rpp;
+  }
   switch (ctx->D) {
-    case 32: rc = launch_levels<32>(pp, ex.n_slots, resident, st); break;
-    case 64: rc = launch_levels<64>(pp, ex.n_slots, resident, st); break;
-    case 128: rc = launch_levels<128>(pp, ex.n_slots, resident, st); break;
-    default: rc = launch_levels<256>(pp, ex.n_slots, resident, st); break;
+    case 32: rc = launch_levels<32>(pp, rp, ex.n_slots, st); break;
+    case 64: rc = launch_levels<64>(pp, rp, ex.n_slots, st); break;
+    case 128: rc = launch_levels<128>(pp, rp, ex.n_slots, st); break;
+    default: rc = launch_levels<256>(pp, rp, ex.n_slots, st); break;
   }
   if (rc) return rc;
   if (!ex.state && !ex.gout) {
@@ -788,6 +822,53 @@ __global__ void quantize_kernel(const float* __restrict__ z, int64_t total, floa
 // sinkhorn_dist_batch and sinkhorn_dist_bounds_batch: the workspace is the
 // routing flags, the list slots, the launch order and (with `state`) the
 // scaled warm-start records.
+// Tables of the 1-D kernels and costs of a context (section 3, the tables
+// before Propositions 2 and 3) in the layout padded to D, index delta + D - 1,
+// built on the host in FP64 and uploaded in one allocation; the seven
+// pointers are set on success (the first one owns the allocation).
+int upload_tables(const pdsink_params& p, int D, int** ge_d, float** gm_d, int** gde_d, float** gdm_d, float** c1_d,
+                  float** cd_d, int** kb_d) {
+  const int n = 2 * D - 1;
+  std::vector<int> ge(n), gde(n);
+  std::vector<float> gm(n), gdm(n), c1(n), cd(n);
+  std::vector<int> kb(n);
+  const double l2e = 1.0 / std::log(2.0);
+  for (int x = 0; x < n; ++x) {
+    const int delta = std::abs(x - (D - 1));
+    if (delta < p.d) {
+      const double c = std::pow((double)delta / p.d, p.p);            // 1-D step cost (|delta| h)^p
+      const double cdl = 2.0 * std::pow((double)delta / (2.0 * p.d), p.p);  // diagonal cost 2 (|delta| h / 2)^p
+      split_pow2(-c / p.gamma * l2e, &ge[x], &gm[x]);
+      split_pow2(-cdl / p.gamma * l2e, &gde[x], &gdm[x]);
+      c1[x] = (float)c;
+      cd[x] = (float)cdl;
+      kb[x] = bf16_word(ge[x], gm[x]);
+    } else {
+      ge[x] = gde[x] = NEG;
+      gm[x] = gdm[x] = 0.0f;
+      c1[x] = cd[x] = 0.0f;
+      kb[x] = -(1 << 27);
+    }
+  }
+  char* base = nullptr;
+  if (hipMalloc(&base, (size_t)n * 4 * 7) != hipSuccess) return PDSINK_ENOMEM;
+  const void* src[7] = {ge.data(), gm.data(), gde.data(), gdm.data(), c1.data(), cd.data(), kb.data()};
+  for (int t = 0; t < 7; ++t) {
+    if (hipMemcpy(base + (size_t)t * n * 4, src[t], (size_t)n * 4, hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(base);
+      return PDSINK_EDEVICE;
+    }
+  }
+  *ge_d = (int*)base;
+  *gm_d = (float*)(base + n * 4);
+  *gde_d = (int*)(base + n * 8);
+  *gdm_d = (float*)(base + n * 12);
+  *c1_d = (float*)(base + n * 16);
+  *cd_d = (float*)(base + n * 20);
+  *kb_d = (int*)(base + n * 24);
+  return PDSINK_OK;
+}
+
 int dist_impl(pdsink_ctx* ctx, int64_t n_pairs, const float* hist_a, const float* hist_b, const int32_t* ia,
               const int32_t* ib, double* state, double* cost, int32_t* iters, float* err, int32_t* status,
               double* upper, double* lower, void* ws, size_t ws_bytes, void* stream, pdsink_done* done = nullptr,
@@ -847,31 +928,7 @@ int pdsink_ctx_create(const pdsink_params* params, int device, pdsink_ctx** out)
     return PDSINK_EINVAL;
   DeviceGuard g(device);
   if (!g.ok) return PDSINK_EDEVICE;
-  // The resident kernel reads the tables of the 128-padded layout: a context
-  // that runs it below d = 65 pads everything to 128.
-  const int D = resident_for(p.d, p.kernel) ? 128 : pad_grid(p.d);
-  const int n = 2 * D - 1;
-  std::vector<int> ge(n), gde(n);
-  std::vector<float> gm(n), gdm(n), c1(n), cd(n);
-  std::vector<int> kb(n);
-  const double l2e = 1.0 / std::log(2.0);
-  for (int x = 0; x < n; ++x) {
-    const int delta = std::abs(x - (D - 1));
-    if (delta < p.d) {
-      const double c = std::pow((double)delta / p.d, p.p);            // 1-D step cost (|delta| h)^p
-      const double cdl = 2.0 * std::pow((double)delta / (2.0 * p.d), p.p);  // diagonal cost 2 (|delta| h / 2)^p
-      split_pow2(-c / p.gamma * l2e, &ge[x], &gm[x]);
-      split_pow2(-cdl / p.gamma * l2e, &gde[x], &gdm[x]);
-      c1[x] = (float)c;
-      cd[x] = (float)cdl;
-      kb[x] = bf16_word(ge[x], gm[x]);
-    } else {
-      ge[x] = gde[x] = NEG;
-      gm[x] = gdm[x] = 0.0f;
-      c1[x] = cd[x] = 0.0f;
-      kb[x] = -(1 << 27);
-    }
-  }
+  const int D = pad_grid(p.d);
   pdsink_ctx* ctx = new (std::nothrow) pdsink_ctx;
   if (!ctx) return PDSINK_ENOMEM;
   std::memset(ctx, 0, sizeof(*ctx));
@@ -886,30 +943,26 @@ int pdsink_ctx_create(const pdsink_params* params, int device, pdsink_ctx** out)
   // With the context's device current: the no-allocation call's scratch.  A
   // failed lookup leaves ctx->scratch NULL, and only that call reports it.
   (void)scratch_lookup(device, &ctx->scratch);
-  char* base = nullptr;
-  const size_t bytes = (size_t)n * 4 * 7;
-  if (hipMalloc(&base, bytes) != hipSuccess) {
-    delete ctx;
-    return PDSINK_ENOMEM;
+  int rc = upload_tables(p, D, &ctx->ge, &ctx->gm, &ctx->gde, &ctx->gdm, &ctx->c1, &ctx->cd, &ctx->kb);
+  if (rc == PDSINK_OK && resident_grid(p.d) && p.kernel != PDSINK_KERNEL_GENERAL) {
+    // the resident kernel reads the 128-padded layout
+    if (D == 128) {
+      ctx->rge = ctx->ge;
+      ctx->rgm = ctx->gm;
+      ctx->rgde = ctx->gde;
+      ctx->rgdm = ctx->gdm;
+      ctx->rc1 = ctx->c1;
+      ctx->rcd = ctx->cd;
+      ctx->rkb = ctx->kb;
+    } else {
+      rc = upload_tables(p, 128, &ctx->rge, &ctx->rgm, &ctx->rgde, &ctx->rgdm, &ctx->rc1, &ctx->rcd, &ctx->rkb);
+      if (rc == PDSINK_OK) ctx->rbase = reinterpret_cast<char*>(ctx->rge);
+    }
   }
-  ctx->ge = (int*)base;
-  ctx->gm = (float*)(base + n * 4);
-  ctx->gde = (int*)(base + n * 8);
-  ctx->gdm = (float*)(base + n * 12);
-  ctx->c1 = (float*)(base + n * 16);
-  ctx->cd = (float*)(base + n * 20);
-  ctx->kb = (int*)(base + n * 24);
-  bool ok = hipMemcpy(ctx->ge, ge.data(), n * 4, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(ctx->gm, gm.data(), n * 4, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(ctx->gde, gde.data(), n * 4, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(ctx->gdm, gdm.data(), n * 4, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(ctx->c1, c1.data(), n * 4, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(ctx->cd, cd.data(), n * 4, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(ctx->kb, kb.data(), n * 4, hipMemcpyHostToDevice) == hipSuccess;
-  if (!ok) {
-    (void)hipFree(base);
+  if (rc != PDSINK_OK) {
+    if (ctx->ge) (void)hipFree(ctx->ge);
     delete ctx;
-    return PDSINK_EDEVICE;
+    return rc;
   }
   *out = ctx;
   return PDSINK_OK;
@@ -919,6 +972,7 @@ void pdsink_ctx_destroy(pdsink_ctx* ctx) {
   if (!ctx) return;
   DeviceGuard g(ctx->device);
   (void)hipFree(ctx->ge);
+  if (ctx->rbase) (void)hipFree(ctx->rbase);
   delete ctx;
 }
 

@@ -33,7 +33,7 @@
 namespace pdsink {
 
 constexpr int FAST_DMAX = 100;                  // largest grid of the variant
-constexpr int RESIDENT_AUTO_DMIN = 65;          // smallest grid it runs by default (the 128-padded class)
+constexpr int RESIDENT_AUTO_DMIN = 65;          // smallest grid it runs by default with FP32 contractions
 constexpr int FAST_KD = 112;                    // FAST_DMAX rounded up to 16
 constexpr int FAST_LDB = FAST_KD + 8;           // BF16 row stride at most (16-byte aligned rows)
 constexpr int FAST_MAXSUSP = 128;               // suspects handled per half step
