@@ -10,10 +10,10 @@ flight.  A launch is one call of ``sinkhorn_dist_batch_notify`` over every
 pair of its requests (a distance is one pair, an assignment k pairs against
 the grid's centroids), which posts each pair's result to pinned host memory
 as soon as that pair is solved: a request completes when its own pairs are
-done, not when the slowest pair of its launch is.  The pool should be no larger than the hardware queues the process
-gets (``GPU_MAX_HW_QUEUES``, read when the HIP runtime starts; four by
-default): streams beyond that share a queue, and a short launch then waits
-behind a long one on the same queue.  More queues let more launches overlap:
+done, not when the slowest pair of its launch is.  The pool should be no
+larger than the hardware queues the process gets (``GPU_MAX_HW_QUEUES``, read
+when the HIP runtime starts; four by default): streams beyond that share a
+queue, and a short launch then waits behind a long one on the same queue.  More queues let more launches overlap:
 a slot is free again once its launch has ended, and while it runs the
 other slots keep the chip busy.  Each turn of ``Server.poll``:
 
@@ -28,9 +28,9 @@ other slots keep the chip busy.  Each turn of ``Server.poll``:
    and within a device-memory budget counted over all launches in flight;
 3. launches the batch on the slot's stream: discretisation of the batch's
    diagrams, a copy of the grid's centroids behind them (assignments), and
-   one distance call over all pairs.  Launches in different slots and at different grids run on the
-   device at the same time; requests that arrive meanwhile wait for the next
-   free slot.
+   one distance call over all pairs.  Launches in different slots and at
+   different grids run on the device at the same time; requests that arrive
+   meanwhile wait for the next free slot.
 
 Every pair's arithmetic depends only on its own two histograms (the library
 routes and orders pairs by their own supports), so a request's result is the
