@@ -1164,27 +1164,48 @@ __device__ __forceinline__ void exact_all(PairSmem<D>& s, const SupList<SPT>& xs
         xm[u] = ok ? x : 0.0f;
         eb[u] = ok ? Px[kr[u]] + Qx[l[u]] : QNONE;
       }
-      for (int id = wave; id < ns; id += PNW) {
-        const int c = suspCell<D, SPT>(s)[id];
-        const int ti = c / D, tj = c % D;
-        int em = QNONE;
+      // Two suspects per wave at a time, so that two independent wave
+      // reductions are in flight; each suspect's terms and their order are
+      // those of a wave that takes it alone.
+      constexpr int NS = 2;
+      for (int id0 = wave * NS; id0 < ns; id0 += PNW * NS) {
+        int ti[NS], tj[NS], em[NS];
+        float acc[NS];
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+          const int c = suspCell<D, SPT>(s)[id0 + t < ns ? id0 + t : id0];
+          ti[t] = c / D;
+          tj[t] = c % D;
+          em[t] = QNONE;
+          acc[t] = 0.0f;
+        }
 #pragma unroll
         for (int u = 0; u < EPL; ++u)
           if (eb[u] != QNONE)
-            em = max(em, eb[u] + ilog2f(xm[u]) + s.tge[ti - kr[u] + D - 1] + s.tge[tj - l[u] + D - 1]);
-        em = wave_max(em);
-        float acc = 0.0f;
+#pragma unroll
+            for (int t = 0; t < NS; ++t)
+              em[t] = max(em[t], eb[u] + ilog2f(xm[u]) + s.tge[ti[t] - kr[u] + D - 1] + s.tge[tj[t] - l[u] + D - 1]);
+#pragma unroll
+        for (int t = 0; t < NS; ++t) em[t] = wave_max(em[t]);
 #pragma unroll
         for (int u = 0; u < EPL; ++u) {
           if (eb[u] != QNONE) {
-            const int i1 = ti - kr[u] + D - 1, i2 = tj - l[u] + D - 1;
-            float mm = xm[u] * s.tgm[i1] * s.tgm[i2];
-            if (WEIGHTED) mm *= (s.tc1[i1] + s.tc1[i2]);
-            acc += ldx(mm, eb[u] + s.tge[i1] + s.tge[i2] - em);
+#pragma unroll
+            for (int t = 0; t < NS; ++t) {
+              const int i1 = ti[t] - kr[u] + D - 1, i2 = tj[t] - l[u] + D - 1;
+              float mm = xm[u] * s.tgm[i1] * s.tgm[i2];
+              if (WEIGHTED) mm *= (s.tc1[i1] + s.tc1[i2]);
+              acc[t] += ldx(mm, eb[u] + s.tge[i1] + s.tge[i2] - em[t]);
+            }
           }
         }
-        acc = wave_sum(acc);
-        if (lane == 0) finish(id, c, em, acc);
+#pragma unroll
+        for (int t = 0; t < NS; ++t) acc[t] = wave_sum(acc[t]);
+        if (lane == 0) {
+#pragma unroll
+          for (int t = 0; t < NS; ++t)
+            if (id0 + t < ns) finish(id0 + t, ti[t] * D + tj[t], em[t], acc[t]);
+        }
       }
       __syncthreads();
       return;
