@@ -223,6 +223,36 @@ def test_resident_kernel_bf16_small_grid_against_converged(pds):
         assert rel(cost[q], r.cost) <= BF16_RTOL, (q, cost[q], r.cost)
 
 
+@pytest.mark.parametrize("d", [72, 90])
+def test_resident_kernel_mid_grids(pds, d):
+    """The resident kernel at K depth 80 (d = 72) and 96 (d = 90), the grids
+    between the small ones and d = 100: FP32 costs against the oracle run for
+    the same iteration count, the stopping iteration within one of the
+    oracle's; then BF16 contractions refined to 1e-5 against the converged
+    FP64 fixed point (pairs 0 and 1; pair 2, masses 33 against 93 at d = 90,
+    converges too slowly for the dense oracle to reach 1e-7 here)."""
+    g = 2e-3
+    D1s, D2s = pdgen.pairs_batch(d, 3, 10, 150)
+    C = dense_C(d)
+    with pds.Context(d, g, tol=1e-4, max_iter=3000, kernel="resident") as ctx:
+        cost, iters, err, st, hist = run_pairs(pds, ctx, D1s, D2s)
+    n = len(D1s)
+    for q in range(n):
+        t = int(iters[q].sum())
+        assert err[q] <= 1e-4 and st[q] == 0, (q, err[q], st[q])
+        r = sinkhorn.sinkhorn(hist[q], hist[n + q], g, max_iter=t, C=C)
+        assert rel(cost[q], r.cost) <= FP32_RTOL, (q, cost[q], r.cost)
+        ro = sinkhorn.sinkhorn(hist[q], hist[n + q], g, tol=1e-4, max_iter=3000, C=C)
+        assert abs(ro.iters - t) <= 1, (q, ro.iters, t)
+    with pds.Context(d, g, tol=1e-5, max_iter=20000, precision="bf16", switch_tol=1.5e-3,
+                     kernel="resident") as ctx:
+        cost_b, iters_b, err_b, st_b, _ = run_pairs(pds, ctx, D1s, D2s)
+    assert np.all(iters_b[:, 0] > 0) and np.all(st_b == 0)
+    for q in (0, 1):
+        rc = sinkhorn.sinkhorn(hist[q], hist[n + q], g, tol=1e-7, max_iter=100000, C=C)
+        assert rel(cost_b[q], rc.cost) <= BF16_RTOL, (q, cost_b[q], rc.cost)
+
+
 def test_edge_cases(pds):
     """Empty diagrams (closed form: all mass to the diagonal), identical
     diagrams, single points, points on the border, d = 2 and d = 128."""
