@@ -679,19 +679,22 @@ def _run_hist_pairs(pds, ctx, A, B):
     return r.cost.cpu().numpy(), r.iters.cpu().numpy(), r.err.cpu().numpy(), r.status.cpu().numpy()
 
 
-@pytest.mark.parametrize("switch_tol", [1.5e-3, 0.8e-3])
-def test_bf16_refine_d100_against_converged(pds, switch_tol):
-    """The grid and contractions the benchmark times (d = 100 padded to 128,
-    BF16 MFMA then FP32 refinement, gamma = 1e-3): refined to 1e-5, each pair's
-    cost is within 1e-3 of the FP64 oracle's converged fixed point (err <= 1e-7;
-    the fixed point is unique).  Pairs 0, 3, 10, 17 of the benchmark batch
+@pytest.mark.parametrize("switch_tol,kernel", [(1.5e-3, "auto"), (0.8e-3, "auto"), (0.8e-3, "general")])
+def test_bf16_refine_d100_against_converged(pds, switch_tol, kernel):
+    """The grid and contractions the benchmark times (d = 100, BF16 MFMA then
+    FP32 refinement, gamma = 1e-3): refined to 1e-5, each pair's cost is
+    within 1e-3 of the FP64 oracle's converged fixed point (err <= 1e-7; the
+    fixed point is unique).  Pairs 0, 3, 10, 17 of the benchmark batch
     (register lists) and a dense upper-triangular histogram against a diagram
     (global lists, suspect arrays in the workspace).  Both the bench's switch
-    point (0.8e-3) and a later one."""
+    point (0.8e-3) and a later one; with the default tiling (the resident
+    kernel for the register lists) and with the general one (the grid padded
+    to 128, 32x32 tiles: the tiling of d = 101 ... 128)."""
     cases = [c for c in golden_cases() if c["kind"] == "converged" and c["d"] == 100]
     assert len(cases) == 5
     hs = [_golden.inputs(c) for c in cases]
-    with pds.Context(100, 1e-3, tol=1e-5, max_iter=20000, precision="bf16", switch_tol=switch_tol) as ctx:
+    with pds.Context(100, 1e-3, tol=1e-5, max_iter=20000, precision="bf16", switch_tol=switch_tol,
+                     kernel=kernel) as ctx:
         cost, iters, err, st = _run_hist_pairs(pds, ctx, [h[0] for h in hs], [h[1] for h in hs])
     for q, c in enumerate(cases):
         assert st[q] == 0 and err[q] <= 1e-5, (c["name"], st[q], err[q])
