@@ -157,12 +157,14 @@ def test_warm_start_same_schedule(pds, d, g, n, lo, hi):
         assert ow.iters < sinkhorn.sinkhorn(hist[q], hist[n + q], g, tol=1e-5, max_iter=20000, C=C).iters
 
 
-def test_benchmark_batch_sampled(pds):
+@pytest.mark.parametrize("kernel", ["auto", "general"])
+def test_benchmark_batch_sampled(pds, kernel):
     """1024 pairs at d=100, gamma=1e-3, tol=1e-3 (the benchmark's launch); three
-    pairs re-run by the oracle at the GPU's iteration counts."""
+    pairs re-run by the oracle at the GPU's iteration counts.  With the default
+    tiling (the resident kernel) and the general one (grid padded to 128)."""
     d, g = 100, 1e-3
     D1s, D2s = pdgen.pairs_batch(0, 1024)
-    with pds.Context(d, g, tol=1e-3, max_iter=5000) as ctx:
+    with pds.Context(d, g, tol=1e-3, max_iter=5000, kernel=kernel) as ctx:
         cost, iters, err, st, hist = run_pairs(pds, ctx, D1s, D2s)
     assert np.all(st == 0) and np.all(err <= 1e-3)
     assert np.all(iters[:, 0] == 0)
