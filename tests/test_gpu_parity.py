@@ -178,12 +178,12 @@ def test_benchmark_batch_sampled(pds, kernel):
         assert rel(cost[q], r.cost) <= FP32_RTOL, (q, cost[q], r.cost)
 
 
-@pytest.mark.parametrize("d,g,kernel", [(50, 1e-3, "auto"), (50, 1e-3, "general"), (32, 5e-3, "auto")])
+@pytest.mark.parametrize("d,g,kernel", [(50, 1e-3, "general"), (32, 5e-3, "auto")])
 def test_bf16_refine_against_converged(pds, d, g, kernel):
     """BF16 contractions then FP32 refinement to 1e-5 match the converged FP64
-    fixed point to 1e-3 relative cost: d = 50 in the default tiling (the
-    resident kernel) and the general one (grid padded to 64), d = 32 (the
-    general kernel's smallest grid class)."""
+    fixed point to 1e-3 relative cost: d = 50 in the general tiling (grid
+    padded to 64; the default tiling there, the resident kernel, has its own
+    test on the same pairs), d = 32 (the general kernel's smallest grid class)."""
     D1s, D2s = pdgen.pairs_batch(3, 3, 20, 200)
     with pds.Context(d, g, tol=1e-5, max_iter=20000, precision="bf16", switch_tol=1.5e-3, kernel=kernel) as ctx:
         cost, iters, err, st, hist = run_pairs(pds, ctx, D1s, D2s)
