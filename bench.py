@@ -229,6 +229,7 @@ def cpu_separable(budget_s: float = 8.0, n_pairs: int = 3) -> dict:
             if t_used >= budget_s:
                 break
     return {"value": its / t_used, "unit": "pair-it/s", "cores": 1, "kind": "cpu separable (log domain, FP64)",
+            "iterations_to_tol": counts,
             "sample": f"benchmark batch from pair 0: {its} pair-iterations in {t_used:.1f} s, pairs run to "
                       f"tol {TOL} took {counts} iterations (the oracle: 157, 495, 348); each iteration also "
                       f"applies K once more for the error check"}

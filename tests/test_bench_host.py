@@ -44,3 +44,14 @@ def test_committed_traffic_record_is_for_these_sources():
                         "sinkhorn_fast_kernel_d100_1024pairs_traffic.json")
     rec = json.load(open(path))
     assert bench.measured_traffic() == (rec["traffic_bytes"] if rec["source_hash"] == bench.source_hash() else None)
+
+
+def test_cpu_separable_stops_where_the_oracle_does():
+    """bench.py's second CPU figure (K applied in the separable form of
+    Proposition 2, log domain) runs Algorithm 1 as the dense oracle does: pair
+    0 of the benchmark batch stops at tol 1e-3 at the iteration count the
+    oracle wrote to the golden file."""
+    gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sinkhorn_golden.json")
+    stops = {c["index"]: c["iters"] for c in json.load(open(gold))["cases"] if c["kind"] == "stop_1e-3"}
+    r = bench.cpu_separable(budget_s=300.0, n_pairs=1)
+    assert r["iterations_to_tol"] == [stops[0]]
