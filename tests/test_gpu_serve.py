@@ -115,6 +115,22 @@ def test_serving_mix_equals_alone(pds):
     print(f"checked against the converged oracle at d = 50: {checked}", flush=True)
     assert checked["distance"] >= 1 and checked["centroid distance"] >= 4
 
+    # the first three distance requests at d = 100 (the resident kernel's
+    # grid), each where its oracle run reaches 1e-7 within 800 iterations
+    C = ground.dense_cost(100)
+    n100, ok100 = 0, 0
+    for s, m in zip(stream, mixed):
+        if s["d"] != 100 or s["kind"] != serve.DIST or n100 >= 3:
+            continue
+        n100 += 1
+        h1, h2 = ground.discretize(s["diagrams"][0], 100), ground.discretize(s["diagrams"][1], 100)
+        r = sinkhorn.sinkhorn(h1, h2, GAMMA, tol=1e-7, max_iter=800, C=C)
+        if r.err <= 1e-7:
+            assert abs(m.cost - r.cost) <= BF16_RTOL * abs(r.cost), (m.rid, m.cost, r.cost)
+            ok100 += 1
+    print(f"d = 100 distances checked against the converged oracle: {ok100} of {n100}", flush=True)
+    assert ok100 >= 1
+
 
 def test_serving_memory_budget_and_latency(pds):
     """A budget that holds the largest 4-request launch of the stream, but not
