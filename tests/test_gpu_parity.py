@@ -536,6 +536,32 @@ def test_kmeans_assign_matches_oracle(pds):
             assert dist[n, assign[n]] <= dist[n].min() * (1 + 1e-12)
 
 
+def test_kmeans_assign_same_schedule(pds):
+    """The assignment's distances on a fixed schedule (tol 0: both sides run
+    exactly 300 iterations, so no stopping decision separates them): every
+    diagram-centroid cost to 1e-5 relative against the FP64 oracle (the FP32
+    bound), and the labels equal wherever the two nearest centroids are
+    further apart than that."""
+    d, g, T = 32, 5e-3, 300
+    diags, _ = pdgen.kmeans_set(4, 24, n_templates=3, template_size=30)
+    hists = [ground.discretize(x, d) for x in diags]
+    cents = [hists[0], hists[1], hists[2]]
+    ol, odist, oit = kmeans.assign(hists, cents, g, tol=0.0, max_iter=T, C=dense_C(d))
+    assert np.all(oit == T)
+    with pds.Context(d, g, tol=0.0, max_iter=T) as ctx:
+        H = torch.from_numpy(np.stack(hists).astype(np.float32)).cuda()
+        Cn = torch.from_numpy(np.stack(cents).astype(np.float32)).cuda()
+        assign, dist, st = pds.kmeans_assign(ctx, H, Cn)
+        torch.cuda.synchronize()
+    dist, assign = dist.cpu().numpy(), assign.cpu().numpy()
+    assert np.all(st.cpu().numpy() & ~1 == 0)   # the iteration cap is the schedule
+    np.testing.assert_allclose(dist, odist, rtol=FP32_RTOL, atol=0)
+    for n in range(len(hists)):
+        srt = np.sort(odist[n])
+        if srt[1] - srt[0] > 4 * FP32_RTOL * srt[0]:
+            assert assign[n] == ol[n], (n, dist[n], odist[n])
+
+
 @pytest.mark.parametrize("d,g,lo,hi", [(16, 1e-2, 10, 40), (40, 5e-3, 20, 80)])
 def test_barycenter_matches_oracle(pds, d, g, lo, hi):
     """Algorithm 2, four outer steps with warm-started inner solves to 1e-6:
